@@ -1,0 +1,228 @@
+/*
+ * vrs.h -- C ABI of the MI355X (gfx950) foveated Gaussian-splat rasterizer.
+ *
+ * The library implements the rendering path of VRSplat (arXiv 2505.10144):
+ * Optimal-Projection preprocessing of 3D Gaussians (Sec. 3 end, Sec. 4.2),
+ * Gaussian/tile instantiation with tangent-plane tile culling (Eq. 4), a
+ * radix sort of tile|depth keys (Sec. 3 tile binning), and per-tile
+ * front-to-back blending (Eq. 2) with per-sample depth resorting (Sec. 4.1)
+ * in which full-resolution fovea tiles and half-resolution periphery tiles
+ * run in one launch (Sec. 4.3, Fig. 5a).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is device memory owned by the caller (for example a
+ *    torch tensor).  The library never allocates, frees or retains caller
+ *    memory and keeps no global mutable state; calls on different streams are
+ *    independent.  Structs passed by pointer are host memory, read during
+ *    the call only.
+ *  - All work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *    the null stream).  The only entry point that synchronises is
+ *    vrs_fovea_plan, which returns the exact work-item count to the host.
+ *  - The return value reports argument errors and launch errors
+ *    (VRS_ERR_INVALID_ARG, VRS_ERR_UNSUPPORTED, VRS_ERR_HIP).  Conditions
+ *    only the device can see are written to *status_dev, an int32 that the
+ *    caller zeroes beforehand; the first error written wins.
+ *  - Floats are IEEE binary32; all per-pair arithmetic is FP32, per-Gaussian
+ *    set-up geometry and the tile test run in FP64 and are rounded once.
+ */
+#ifndef VRS_H
+#define VRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* vrs_stream_t; /* hipStream_t */
+
+/* Status codes (return values and *status_dev). */
+#define VRS_OK 0
+#define VRS_ERR_INVALID_ARG (-1)
+#define VRS_ERR_CAPACITY (-2)
+#define VRS_ERR_HIP (-3)
+#define VRS_ERR_UNSUPPORTED (-4)
+
+/* Limits. */
+#define VRS_MAX_VIEWS 32
+#define VRS_MAX_WINDOW 32
+#define VRS_RECORD_FLOATS 32 /* floats per projected Gaussian record (128 B) */
+
+/* Render work-item classes (Sec. 4.3): LOW = 32x32 periphery tile shaded as
+ * 16x16 samples at 2x2-group centres; HIGH = 16x16 fovea subtile at full
+ * resolution; HYBRID = transitional subtile (full resolution blended with its
+ * 2x2-group mean by the continuous mask); PLAIN = 16x16 tile of a
+ * non-foveated view. */
+#define VRS_CLASS_LOW 0
+#define VRS_CLASS_HIGH 1
+#define VRS_CLASS_HYBRID 2
+#define VRS_CLASS_PLAIN 3
+
+/* Gaussians (Sec. 3 Eq. 1; optimised parameters of Sec. 4.1), structure of
+ * arrays, FP32, device memory:
+ *   means[3][n]          world-space mean
+ *   log_scales[3][n]     natural log of the per-axis standard deviation
+ *   quats[4][n]          rotation (w, x, y, z), any non-zero length
+ *   opacity_logits[n]    opacity = 1 / (1 + exp(-o))
+ *   sh[K][3][n]          real SH coefficients, K = (sh_degree+1)^2, index
+ *                        k = l^2 + l + m, Condon-Shortley phase; colour =
+ *                        max(0, sum_k sh_k Y_k(v) + 0.5), v = unit vector from
+ *                        the eye centre to the mean. */
+typedef struct {
+    int32_t n;
+    int32_t sh_degree; /* 0..3 */
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opacity_logits;
+    const float* sh;
+} vrs_gaussians;
+
+/* Pinhole camera (Sec. 5; App. D varies focal length and resolution).
+ * x_cam = R x_world + t with world_to_cam = [R | t] row-major 3x4; camera
+ * axes x right, y down, z forward; square pixels with focal length
+ * f = (width/2) / tan(fov_x/2) pixels; principal point (cx, cy) in pixels;
+ * pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
+typedef struct {
+    float world_to_cam[12];
+    float fov_x_deg;
+    float cx, cy;
+    int32_t width, height;
+} vrs_camera;
+
+/* Fovea (Sec. 4.3): mask w = clamp((rho (1 + b) - e) / (rho b), 0, 1) of the
+ * angle e between a pixel's ray and the ray through center_px, with radius
+ * rho = radius_deg and band fraction b = band_frac (the paper uses a 10 %
+ * linear band).  enabled = 0 renders the view plainly with 16x16 tiles. */
+typedef struct {
+    int32_t enabled;
+    float center_px[2];
+    float radius_deg;
+    float band_frac;
+} vrs_fovea;
+
+/* Renderer knobs.  tile: 16 (plain views) -- foveated views always use 32x32
+ * sort tiles split into 16x16 subtiles; window: per-sample resort window
+ * length W, 1..32 (Sec. 4.1); blend_batch: list entries staged per wave and
+ * batch, 64 (performance only, never changes the output).
+ * z_near: near cull on camera z; alpha_min: culling and skip threshold
+ * (1/255, Sec. 4.2); alpha_max: alpha clamp (0.99); t_min: transmittance at
+ * which a sample stops (1e-4); dilation: px^2 added to the 2D covariance
+ * (App. D); background: RGB composited behind. */
+typedef struct {
+    int32_t tile;
+    int32_t window;
+    int32_t blend_batch;
+    float z_near;
+    float alpha_min;
+    float alpha_max;
+    float t_min;
+    float dilation;
+    float background[3];
+} vrs_params;
+
+/* Buffer sizes for one configuration (all bytes unless noted). */
+typedef struct {
+    size_t proj_bytes;       /* records: n_views * n * VRS_RECORD_FLOATS floats   */
+    size_t counts_bytes;     /* uint32 counts[n_views][n]                         */
+    uint32_t tiles_total;    /* sum over views of sort-grid tiles (ranges rows)    */
+    uint32_t items_max;      /* upper bound on render work items                   */
+    size_t plan_bytes;       /* work list + per-view subtile class maps            */
+    size_t sort_ws_bytes;    /* vrs_sort workspace for `capacity` instances        */
+    size_t render_ws_bytes;  /* vrs_render_foveated workspace (pre-compose images) */
+} vrs_sizes;
+
+/* Sizes of every buffer the other entry points need.  `capacity` is the
+ * instance capacity the caller intends to pass to vrs_sort.  Host-only, no
+ * device work.  Returns VRS_ERR_INVALID_ARG for bad arguments. */
+int vrs_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* foveas,
+                       int32_t n_views, const vrs_params* p, size_t capacity,
+                       vrs_sizes* out);
+
+/* Foveation map (Sec. 4.3: "this mapping can be efficiently computed at the
+ * start of each render pass and enables us to compute the exact number of
+ * blocks to launch"; precomputed once per eye and reused).  Writes into
+ * `plan` (plan_bytes from vrs_workspace_size) the class of every 16x16
+ * subtile of every view and a compact list of render work items: per
+ * foveated view, one LOW item per periphery 32x32 tile and one HIGH/HYBRID
+ * item per in-image subtile of a split tile; per plain view, one PLAIN item
+ * per 16x16 tile.  Synchronises `stream` and returns the exact item count in
+ * *n_items.  Classes are decided in FP64. */
+int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                   const vrs_params* p, void* plan, size_t plan_bytes,
+                   uint32_t* n_items, vrs_stream_t stream);
+
+/* Per-Gaussian preprocessing (Sec. 3 Eq. 1, Optimal Projection of Sec. 3 end
+ * and Sec. 4.2, SH colour; one thread per Gaussian covering every view).
+ * Writes per view and Gaussian a record of VRS_RECORD_FLOATS floats into
+ * `proj` ([n_views][n][32], 128-byte aligned rows) and the exact number of
+ * tiles that survive the tangent-plane tile test (Eq. 4) into
+ * counts[n_views][n] (0 for culled Gaussians: camera z <= z_near, opacity <
+ * alpha_min, non-finite parameters).  Sort grids: 32x32 for foveated views,
+ * p->tile (16) otherwise. */
+int vrs_preprocess(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
+                   int32_t n_views, const vrs_params* p, void* proj, uint32_t* counts,
+                   int32_t* status_dev, vrs_stream_t stream);
+
+/* Gaussian/tile instantiation (Sec. 3 tile binning; Eq. 4 culling; per-tile
+ * depth at the back-projected maximum point, Sec. 4.2).  Exclusive scan of
+ * counts, then for each surviving (Gaussian, tile) pair writes
+ *   keys[i] = (global_tile << 32) | ord(float32(depth)),  gids[i] = Gaussian
+ * in (view, Gaussian, tile) order, where global_tile = view offset + ty*ntx +
+ * tx and ord maps float order to unsigned order.  *n_inst_dev receives the
+ * total.  If it exceeds `capacity`, *status_dev = VRS_ERR_CAPACITY, only the
+ * first `capacity` pairs are written and *n_inst_dev still holds the
+ * required count.  `ws` must hold sort_ws_bytes. */
+int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
+                  int32_t n_views, const vrs_params* p, const uint32_t* counts,
+                  uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev,
+                  void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream);
+
+/* Stable LSD radix sort of (keys, vals) by the low `key_bits` bits of the
+ * key (Sec. 3: the instances are sorted).  Equal keys keep their input order,
+ * so instances written in Gaussian order come out ordered by (key, gid).
+ * Sorts min(*n_dev, capacity) pairs in place; `ws` must hold
+ * vrs_sort_pairs_workspace_size(capacity) bytes. */
+int vrs_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity,
+                   int32_t key_bits, void* ws, size_t ws_bytes, vrs_stream_t stream);
+size_t vrs_sort_pairs_workspace_size(size_t capacity);
+
+/* Tile ranges of sorted keys: ranges[t] = {first, last + 1} of global tile t,
+ * {0, 0} for empty tiles.  ranges has tiles_total rows of two uint32. */
+int vrs_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity,
+                    uint32_t tiles_total, uint32_t* ranges, vrs_stream_t stream);
+
+/* vrs_duplicate + vrs_sort_pairs + vrs_tile_ranges. */
+int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
+             int32_t n_views, const vrs_params* p, const uint32_t* counts,
+             uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev,
+             uint32_t* ranges, void* ws, size_t ws_bytes, int32_t* status_dev,
+             vrs_stream_t stream);
+
+/* Per-tile blending in one launch over every work item of every view (Eq. 2;
+ * Sec. 4.1 per-sample resorting with a window of p->window entries; Sec. 4.3
+ * LOW/HIGH/HYBRID items), followed by the periphery reconstruction of
+ * foveated views (nearest-neighbour upsampling and a 3x3 binomial blur of
+ * LOW pixels, Sec. 4.3).  proj/n: the records written by vrs_preprocess
+ * for n Gaussians; gids/ranges: the sorted instances of vrs_sort.  rgba[v] is a device pointer to view v's output,
+ * planar float [4][height][width] (R, G, B, alpha = 1 - T).  `plan` and
+ * n_items come from vrs_fovea_plan for the same cameras/foveas/params;
+ * `ws` must hold render_ws_bytes. */
+int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
+                        const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                        const vrs_params* p, const void* plan, uint32_t n_items,
+                        float* const* rgba, void* ws, size_t ws_bytes,
+                        int32_t* status_dev, vrs_stream_t stream);
+
+/* Human-readable name of a status code. */
+const char* vrs_status_string(int code);
+
+/* Library version string ("vrs <major>.<minor> gfx950"). */
+const char* vrs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VRS_H */

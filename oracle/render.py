@@ -48,6 +48,7 @@ class OracleOptions:
     workers: int = 1
     record: bool = False
     eps_inst: float = 1e-9                # |ln alpha_hat - ln alpha_min| for instance flags
+    shade: bool = True                    # False: stop after keys and ranges
 
 
 def preprocess_view(scene, cam, params):
@@ -258,6 +259,10 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
             d[int(gt - lo)] = (sgids[s:e], amb_next[s:e])
         lists.append(d)
 
+    if not opts.shade:
+        return dict(pre=pres, grids=grids, view_offsets=offs, n_tiles=off, inst_tile=all_tile,
+                    inst_gid=all_gid, inst_depth=all_dep, inst_border=all_border, keys=skeys,
+                    gids=sgids, depths=sdep, ranges=ranges, stats=dict(n_inst=int(len(skeys))))
     # Step 4: shading jobs.
     jobs = []
     classes = []

@@ -1,0 +1,381 @@
+// The extern "C" entry points declared in include/vrs.h: argument
+// validation, per-view tables, buffer layouts and kernel launches.
+#include <math.h>
+#include <string.h>
+
+#include "vrs_internal.h"
+
+namespace vrs {
+
+int launch_status(hipError_t e) { return e == hipSuccess ? VRS_OK : VRS_ERR_HIP; }
+
+// Launchers defined in the kernel translation units.
+int launch_preprocess(const GaussPtrs&, const GeoViews&, const Knobs&, float*, uint32_t*, hipStream_t);
+int launch_duplicate(const GaussPtrs&, const GeoViews&, const Knobs&, const uint32_t*, uint64_t*, uint32_t*,
+                     size_t, uint32_t*, void*, int*, hipStream_t);
+size_t scan_ws_bytes(size_t n);
+size_t sort_ws_bytes(size_t capacity);
+int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, hipStream_t);
+int launch_tile_ranges(const uint64_t*, const uint32_t*, size_t, uint32_t, uint32_t*, hipStream_t);
+int launch_render(const float*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, uint32_t,
+                  const RenderViews&, const Knobs&, int, const uint8_t*, hipStream_t);
+bool window_supported(int w);
+
+int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, void* plan, size_t items_max, hipStream_t s);
+}  // namespace vrs
+
+namespace {
+
+using namespace vrs;
+
+struct ViewLayout {
+    double f;
+    int foveated;
+    int T, ntx, nty;
+    int ntx16, nty16;
+    uint32_t tile_off;
+    uint32_t cls_off;
+    size_t pre_off;  // float offset into the render workspace
+};
+
+struct Layout {
+    int n_views;
+    ViewLayout v[VRS_MAX_VIEWS];
+    uint32_t tiles_total;
+    uint32_t items_max;
+    size_t cls_bytes;
+    size_t plan_bytes;
+    size_t render_ws_floats;
+};
+
+bool finite_f(float x) { return isfinite(x); }
+
+int check_params(const vrs_params* p) {
+    if (!p) return VRS_ERR_INVALID_ARG;
+    if (p->tile != 16 && p->tile != 32) return VRS_ERR_INVALID_ARG;
+    if (p->window < 1 || p->window > VRS_MAX_WINDOW) return VRS_ERR_INVALID_ARG;
+    if (!window_supported(p->window)) return VRS_ERR_UNSUPPORTED;
+    if (p->blend_batch != 64) return VRS_ERR_UNSUPPORTED;
+    if (!(p->z_near > 0.f) || !finite_f(p->z_near)) return VRS_ERR_INVALID_ARG;
+    if (!(p->alpha_min > 0.f && p->alpha_min < 1.f)) return VRS_ERR_INVALID_ARG;
+    if (!(p->alpha_max >= p->alpha_min && p->alpha_max <= 1.f)) return VRS_ERR_INVALID_ARG;
+    if (!(p->t_min > 0.f && p->t_min < 1.f)) return VRS_ERR_INVALID_ARG;
+    if (!(p->dilation >= 0.f) || !finite_f(p->dilation)) return VRS_ERR_INVALID_ARG;
+    for (int c = 0; c < 3; ++c)
+        if (!finite_f(p->background[c])) return VRS_ERR_INVALID_ARG;
+    return VRS_OK;
+}
+
+int make_layout(const vrs_camera* cams, const vrs_fovea* foveas, int n_views, const vrs_params* p, Layout& L) {
+    if (!cams || !foveas || n_views < 1 || n_views > VRS_MAX_VIEWS) return VRS_ERR_INVALID_ARG;
+    int rc = check_params(p);
+    if (rc != VRS_OK) return rc;
+    L.n_views = n_views;
+    uint64_t tiles = 0, items = 0, cls = 0, pre = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const vrs_camera& c = cams[v];
+        const vrs_fovea& fv = foveas[v];
+        if (c.width < 1 || c.height < 1 || c.width > (1 << 16) || c.height > (1 << 16)) return VRS_ERR_INVALID_ARG;
+        if (!(c.fov_x_deg > 0.f && c.fov_x_deg < 180.f)) return VRS_ERR_INVALID_ARG;
+        for (int k = 0; k < 12; ++k)
+            if (!finite_f(c.world_to_cam[k])) return VRS_ERR_INVALID_ARG;
+        if (!finite_f(c.cx) || !finite_f(c.cy)) return VRS_ERR_INVALID_ARG;
+        if (fv.enabled) {
+            if (!finite_f(fv.center_px[0]) || !finite_f(fv.center_px[1])) return VRS_ERR_INVALID_ARG;
+            if (!(fv.radius_deg >= 0.f && fv.radius_deg <= 180.f)) return VRS_ERR_INVALID_ARG;
+            if (!(fv.band_frac >= 0.f) || !finite_f(fv.band_frac)) return VRS_ERR_INVALID_ARG;
+        }
+        ViewLayout& V = L.v[v];
+        V.f = (double(c.width) / 2.0) / tan(double(c.fov_x_deg) * (M_PI / 180.0) / 2.0);
+        V.foveated = fv.enabled ? 1 : 0;
+        V.T = V.foveated ? 32 : p->tile;
+        V.ntx = (c.width + V.T - 1) / V.T;
+        V.nty = (c.height + V.T - 1) / V.T;
+        const int nt32x = (c.width + 31) / 32, nt32y = (c.height + 31) / 32;
+        V.ntx16 = 2 * nt32x;
+        V.nty16 = 2 * nt32y;
+        V.tile_off = uint32_t(tiles);
+        tiles += uint64_t(V.ntx) * V.nty;
+        items += (V.T == 32) ? 4ull * V.ntx * V.nty : uint64_t(V.ntx) * V.nty;
+        V.cls_off = uint32_t(cls);
+        if (V.foveated) cls += uint64_t(V.ntx16) * V.nty16;
+        V.pre_off = size_t(pre);
+        if (V.foveated) pre += 4ull * c.width * c.height;
+    }
+    if (tiles >= (1ull << 31) || items >= (1ull << 23)) return VRS_ERR_UNSUPPORTED;
+    L.tiles_total = uint32_t(tiles);
+    L.items_max = uint32_t(items);
+    L.cls_bytes = size_t(cls);
+    L.plan_bytes = kPlanItemsOff + size_t(items) * 4 + ((size_t(cls) + 255) & ~size_t(255));
+    L.render_ws_floats = size_t(pre);
+    return VRS_OK;
+}
+
+int check_gaussians(const vrs_gaussians* g) {
+    if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return VRS_ERR_INVALID_ARG;
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+        return VRS_ERR_INVALID_ARG;
+    return VRS_OK;
+}
+
+GaussPtrs gauss_ptrs(const vrs_gaussians* g) {
+    GaussPtrs p;
+    p.means = g->means;
+    p.log_scales = g->log_scales;
+    p.quats = g->quats;
+    p.opac = g->opacity_logits;
+    p.sh = g->sh;
+    p.n = g->n;
+    p.sh_degree = g->sh_degree;
+    return p;
+}
+
+Knobs knobs(const vrs_params* p) {
+    Knobs k;
+    k.z_near = p->z_near;
+    k.alpha_min = p->alpha_min;
+    k.alpha_max = p->alpha_max;
+    k.t_min = p->t_min;
+    k.dilation = p->dilation;
+    for (int c = 0; c < 3; ++c) k.bg[c] = p->background[c];
+    return k;
+}
+
+GeoViews geo_views(const vrs_camera* cams, const Layout& L) {
+    GeoViews G;
+    memset(&G, 0, sizeof(G));
+    G.n = L.n_views;
+    for (int v = 0; v < L.n_views; ++v) {
+        GeoView& o = G.v[v];
+        const ViewLayout& V = L.v[v];
+        o.f = V.f;
+        for (int k = 0; k < 3; ++k) {
+            for (int j = 0; j < 3; ++j) o.R[3 * k + j] = cams[v].world_to_cam[4 * k + j];
+            o.t[k] = cams[v].world_to_cam[4 * k + 3];
+        }
+        o.cx = cams[v].cx;
+        o.cy = cams[v].cy;
+        o.W = cams[v].width;
+        o.H = cams[v].height;
+        o.T = V.T;
+        o.ntx = V.ntx;
+        o.nty = V.nty;
+        o.tile_off = V.tile_off;
+    }
+    return G;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int key_bits_for(uint32_t tiles_total) {
+    int b = 0;
+    while (b < 32 && (uint64_t(1) << b) < uint64_t(tiles_total)) ++b;
+    return 32 + b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vrs_status_string(int code) {
+    switch (code) {
+        case VRS_OK: return "VRS_OK";
+        case VRS_ERR_INVALID_ARG: return "VRS_ERR_INVALID_ARG";
+        case VRS_ERR_CAPACITY: return "VRS_ERR_CAPACITY";
+        case VRS_ERR_HIP: return "VRS_ERR_HIP";
+        case VRS_ERR_UNSUPPORTED: return "VRS_ERR_UNSUPPORTED";
+        default: return "VRS_ERR_UNKNOWN";
+    }
+}
+
+const char* vrs_version(void) { return "vrs 0.1 gfx950"; }
+
+int vrs_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                       const vrs_params* p, size_t capacity, vrs_sizes* out) {
+    if (!out || n < 0) return VRS_ERR_INVALID_ARG;
+    Layout L;
+    const int rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    const size_t nv = size_t(n_views) * size_t(n);
+    out->proj_bytes = nv * kRec * sizeof(float);
+    out->counts_bytes = nv * sizeof(uint32_t);
+    out->tiles_total = L.tiles_total;
+    out->items_max = L.items_max;
+    out->plan_bytes = L.plan_bytes;
+    const size_t a = scan_ws_bytes(nv), b = sort_ws_bytes(capacity);
+    out->sort_ws_bytes = a > b ? a : b;
+    out->render_ws_bytes = L.render_ws_floats * sizeof(float);
+    return VRS_OK;
+}
+
+int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,
+                   void* plan, size_t plan_bytes, uint32_t* n_items, vrs_stream_t stream) {
+    Layout L;
+    int rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    if (!plan || !n_items || plan_bytes < L.plan_bytes || !aligned(plan, 256)) return VRS_ERR_INVALID_ARG;
+    FovView fv[VRS_MAX_VIEWS];
+    ItemViews iv;
+    memset(fv, 0, sizeof(fv));
+    memset(&iv, 0, sizeof(iv));
+    iv.n = n_views;
+    for (int v = 0; v < n_views; ++v) {
+        const ViewLayout& V = L.v[v];
+        const vrs_camera& c = cams[v];
+        const vrs_fovea& f = foveas[v];
+        FovView& o = fv[v];
+        o.f = V.f;
+        o.cx = c.cx;
+        o.cy = c.cy;
+        o.dc[0] = (double(f.center_px[0]) - double(c.cx)) / V.f;
+        o.dc[1] = (double(f.center_px[1]) - double(c.cy)) / V.f;
+        o.dc[2] = 1.0;
+        o.dcn = sqrt(o.dc[0] * o.dc[0] + o.dc[1] * o.dc[1] + 1.0);
+        const double rho = double(f.radius_deg) * (M_PI / 180.0);
+        const double b = double(f.band_frac);
+        o.all_low = rho <= 0.0 ? 1 : 0;
+        const double outer = rho * (1.0 + b);
+        o.cos_low = outer >= M_PI ? -2.0 : cos(outer);
+        o.cos_high = rho >= M_PI ? -2.0 : cos(rho);
+        o.W = c.width;
+        o.H = c.height;
+        o.ntx32 = (c.width + 31) / 32;
+        o.nty32 = (c.height + 31) / 32;
+        o.ntx16 = V.ntx16;
+        o.nty16 = V.nty16;
+        o.cls_off = V.cls_off;
+        ItemView& it = iv.v[v];
+        it.foveated = V.foveated;
+        it.T = V.T;
+        it.ntx = V.ntx;
+        it.ntx16 = V.ntx16;
+        it.ntiles = V.ntx * V.nty;
+        it.W = c.width;
+        it.H = c.height;
+        it.cls_off = V.cls_off;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    rc = launch_fovea_plan(fv, iv, plan, L.items_max, s);
+    if (rc != VRS_OK) return rc;
+    uint32_t cnt = 0;
+    if (hipMemcpyAsync(&cnt, plan, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return VRS_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return VRS_ERR_HIP;
+    *n_items = cnt;
+    return VRS_OK;
+}
+
+int vrs_preprocess(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                   const vrs_params* p, void* proj, uint32_t* counts, int32_t* status_dev, vrs_stream_t stream) {
+    (void)status_dev;
+    int rc = check_gaussians(g);
+    if (rc != VRS_OK) return rc;
+    Layout L;
+    rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    if (g->n > 0 && (!proj || !counts || !aligned(proj, 16))) return VRS_ERR_INVALID_ARG;
+    return launch_preprocess(gauss_ptrs(g), geo_views(cams, L), knobs(p), static_cast<float*>(proj), counts,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
+int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                  const vrs_params* p, const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
+                  uint32_t* n_inst_dev, void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream) {
+    int rc = check_gaussians(g);
+    if (rc != VRS_OK) return rc;
+    Layout L;
+    rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    const size_t nv = size_t(n_views) * size_t(g->n);
+    if (!n_inst_dev || (nv > 0 && (!counts || !ws)) || (capacity > 0 && (!keys || !gids))) return VRS_ERR_INVALID_ARG;
+    if (capacity > 0xFFFFFFFFull || nv > 0xFFFFFFFFull) return VRS_ERR_UNSUPPORTED;
+    if (ws_bytes < scan_ws_bytes(nv) || !aligned(keys, 8) || !aligned(ws, 16)) return VRS_ERR_INVALID_ARG;
+    return launch_duplicate(gauss_ptrs(g), geo_views(cams, L), knobs(p), counts, keys, gids, capacity, n_inst_dev,
+                            ws, status_dev, reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t vrs_sort_pairs_workspace_size(size_t capacity) { return sort_ws_bytes(capacity); }
+
+int vrs_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity, int32_t key_bits,
+                   void* ws, size_t ws_bytes, vrs_stream_t stream) {
+    if (key_bits < 0 || key_bits > 64 || !n_dev) return VRS_ERR_INVALID_ARG;
+    if (capacity > 0xFFFFFFFFull) return VRS_ERR_UNSUPPORTED;
+    if (capacity > 0 && (!keys || !vals || !ws || ws_bytes < sort_ws_bytes(capacity) || !aligned(keys, 8) ||
+                         !aligned(ws, 16)))
+        return VRS_ERR_INVALID_ARG;
+    return launch_sort_pairs(keys, vals, n_dev, capacity, key_bits, ws, reinterpret_cast<hipStream_t>(stream));
+}
+
+int vrs_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity, uint32_t tiles_total,
+                    uint32_t* ranges, vrs_stream_t stream) {
+    if (!n_dev || (tiles_total > 0 && !ranges) || (capacity > 0 && !keys)) return VRS_ERR_INVALID_ARG;
+    return launch_tile_ranges(keys, n_dev, capacity, tiles_total, ranges, reinterpret_cast<hipStream_t>(stream));
+}
+
+int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+             const vrs_params* p, const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
+             uint32_t* n_inst_dev, uint32_t* ranges, void* ws, size_t ws_bytes, int32_t* status_dev,
+             vrs_stream_t stream) {
+    Layout L;
+    int rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    rc = vrs_duplicate(g, cams, foveas, n_views, p, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
+                       status_dev, stream);
+    if (rc != VRS_OK) return rc;
+    if (capacity > 0) {
+        rc = vrs_sort_pairs(keys, gids, n_inst_dev, capacity, key_bits_for(L.tiles_total), ws, ws_bytes, stream);
+        if (rc != VRS_OK) return rc;
+    }
+    return vrs_tile_ranges(keys, n_inst_dev, capacity, L.tiles_total, ranges, stream);
+}
+
+int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
+                        const vrs_camera* cams,
+                        const vrs_fovea* foveas, int32_t n_views, const vrs_params* p, const void* plan,
+                        uint32_t n_items, float* const* rgba, void* ws, size_t ws_bytes, int32_t* status_dev,
+                        vrs_stream_t stream) {
+    (void)status_dev;
+    Layout L;
+    int rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    if (n < 0 || !plan || !rgba || !ranges || n_items > L.items_max) return VRS_ERR_INVALID_ARG;
+    if (n_items > 0 && (!proj || !gids || !aligned(proj, 16))) return VRS_ERR_INVALID_ARG;
+    if (L.render_ws_floats > 0 && (!ws || ws_bytes < L.render_ws_floats * sizeof(float)))
+        return VRS_ERR_INVALID_ARG;
+    RenderViews R;
+    memset(&R, 0, sizeof(R));
+    R.n = n_views;
+    for (int v = 0; v < n_views; ++v) {
+        const ViewLayout& V = L.v[v];
+        const vrs_camera& c = cams[v];
+        const vrs_fovea& f = foveas[v];
+        RenderView& o = R.v[v];
+        if (!rgba[v]) return VRS_ERR_INVALID_ARG;
+        o.out = rgba[v];
+        o.pre = V.foveated ? static_cast<float*>(ws) + V.pre_off : rgba[v];
+        o.f = float(V.f);
+        o.cx = c.cx;
+        o.cy = c.cy;
+        const double d0 = (double(f.center_px[0]) - double(c.cx)) / V.f;
+        const double d1 = (double(f.center_px[1]) - double(c.cy)) / V.f;
+        const double dn = sqrt(d0 * d0 + d1 * d1 + 1.0);
+        o.fdir[0] = float(d0 / dn);
+        o.fdir[1] = float(d1 / dn);
+        o.fdir[2] = float(1.0 / dn);
+        o.rho = float(double(f.radius_deg) * (M_PI / 180.0));
+        o.band = f.band_frac;
+        o.W = c.width;
+        o.H = c.height;
+        o.T = V.T;
+        o.ntx = V.ntx;
+        o.ntx16 = V.ntx16;
+        o.tile_off = V.tile_off;
+        o.cls_off = V.cls_off;
+        o.foveated = V.foveated;
+    }
+    const uint8_t* cls = static_cast<const uint8_t*>(plan) + kPlanItemsOff + size_t(L.items_max) * 4;
+    const uint32_t* items = reinterpret_cast<const uint32_t*>(static_cast<const char*>(plan) + kPlanItemsOff);
+    return launch_render(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items, R, knobs(p),
+                         p->window, cls, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

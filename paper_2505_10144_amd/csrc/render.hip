@@ -1,0 +1,331 @@
+// K6: per-tile blending in one launch over the work items of every view, and
+// K7: periphery reconstruction of foveated views.
+//
+// K6 (Eq. 2; Sec. 4.1 per-pixel resorting; Sec. 4.3 single-pass foveation).
+// One 256-thread block per work item.  Each thread owns one sample: a pixel
+// of a 16x16 tile/subtile, or the centre of a 2x2 group of a 32x32 LOW tile
+// (half resolution).  The four waves of a block walk the tile's sorted list
+// independently: each wave stages 64 list entries at a time in its own LDS
+// slice (one record per lane, so there is no block barrier) and then every
+// lane evaluates the splat for its sample from broadcast LDS reads.  Entries
+// whose alpha reaches alpha_min go into a per-sample window of W entries kept
+// sorted in registers; when it overflows the entry with the smallest depth is
+// blended.  A wave stops as soon as all of its samples have stopped.
+//
+// Per-pair arithmetic (pixel offset delta = sample - mean image point):
+//   z = M delta / h, h = 1 + a3 . delta;  alpha = opacity * 2^(-|z|^2 / h^2)
+//   (M carries the factor that turns e^(-D^2/2) into a power of two);
+//   the pass test |z|^2 <= KAP h^2 needs no division;
+//   depth t = (n0 + nx dx + ny dy) / |w0 + dx wx + dy wy|^2 (ray depth of
+//   maximum density, ordered identically to the unit-ray depth).
+#include <float.h>
+
+#include "vrs_internal.h"
+
+namespace vrs {
+
+constexpr int kRenderThreads = 256;
+constexpr int kBatch = 64;      // entries staged per wave and batch
+constexpr int kStage = 7;       // float4 per staged entry
+
+struct Slot {
+    float t, a, r, g, b;
+};
+
+template <int W>
+struct Window {
+    float t[W], a[W], r[W], g[W], b[W];
+
+    __device__ inline void init() {
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            t[i] = -FLT_MAX;  // placeholders: blending them is a no-op (alpha 0)
+            a[i] = 0.f; r[i] = 0.f; g[i] = 0.f; b[i] = 0.f;
+        }
+    }
+
+    // Insert x, then remove and return the entry with the smallest depth.
+    // With c[i] = (t[i] <= x.t) (a prefix of the sorted window), the result
+    // is: emitted = c[0] ? slot 0 : x, and slot i becomes slot i+1 if
+    // c[i+1], else x if c[i], else stays -- so a window entry wins ties (it
+    // arrived earlier).  Slots are rewritten in ascending order, each from
+    // itself and its not-yet-rewritten neighbour, so the update is in place.
+    // Pushing an entry with t = -inf and alpha = 0 leaves the window
+    // unchanged and returns that entry, whose blend is a no-op: lanes with
+    // nothing to insert run the same instructions as the others.
+    __device__ inline Slot push(const Slot& x) {
+        bool c[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) c[i] = t[i] <= x.t;
+        Slot e;
+        e.t = c[0] ? t[0] : x.t;
+        e.a = c[0] ? a[0] : x.a;
+        e.r = c[0] ? r[0] : x.r;
+        e.g = c[0] ? g[0] : x.g;
+        e.b = c[0] ? b[0] : x.b;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            t[i] = c[i] ? x.t : t[i];
+            a[i] = c[i] ? x.a : a[i];
+            r[i] = c[i] ? x.r : r[i];
+            g[i] = c[i] ? x.g : g[i];
+            b[i] = c[i] ? x.b : b[i];
+            if (i + 1 < W) {
+                t[i] = c[i + 1] ? t[i + 1] : t[i];
+                a[i] = c[i + 1] ? a[i + 1] : a[i];
+                r[i] = c[i + 1] ? r[i + 1] : r[i];
+                g[i] = c[i + 1] ? g[i + 1] : g[i];
+                b[i] = c[i + 1] ? b[i + 1] : b[i];
+            }
+            // Keep each slot's update together so that it can be done in
+            // the slot's own registers (no rotation copies at the loop edge).
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return e;
+    }
+};
+
+struct Accum {
+    float T, cr, cg, cb;
+    bool alive;
+
+    // Front-to-back blending of one entry; the entry that would take T below
+    // t_min is not blended and stops the sample.  Branch-free so that the
+    // window state never merges across divergent paths.
+    __device__ inline void blend(float a, float r, float g, float b, float t_min) {
+        const float Tn = T * (1.f - a);
+        const bool stop = Tn < t_min;
+        const bool ok = alive && !stop;
+        const float w = ok ? T * a : 0.f;
+        cr = fmaf(w, r, cr);
+        cg = fmaf(w, g, cg);
+        cb = fmaf(w, b, cb);
+        T = ok ? Tn : T;
+        alive = ok;
+    }
+};
+
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int W>
+__global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restrict__ proj, uint32_t n_gauss,
+                                                           const uint32_t* __restrict__ gids,
+                                                           const uint32_t* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ items,
+                                                           RenderViews views, Knobs kn) {
+    __shared__ float4 stage[kRenderThreads / 64][kBatch][kStage];
+    const uint32_t item = items[blockIdx.x];
+    const int v = item_view(item);
+    const int cls = item_class(item);
+    const int sub = item_sub(item);
+    const uint32_t tile = item_tile(item);
+    const RenderView& V = views.v[v];
+    const int T = V.foveated ? 32 : V.T;
+    const int tx = int(tile % uint32_t(V.ntx)), ty = int(tile / uint32_t(V.ntx));
+    const int ox = tx * T, oy = ty * T;  // sort-tile origin (pixels)
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+
+    // Sample of this thread, relative to the tile origin.
+    int px, py;      // first pixel covered
+    float sx, sy;    // sample position relative to (ox, oy)
+    if (cls == VRS_CLASS_LOW) {
+        const int gx = t & 15, gy = t >> 4;
+        px = ox + 2 * gx;
+        py = oy + 2 * gy;
+        sx = float(2 * gx + 1);
+        sy = float(2 * gy + 1);
+    } else {
+        // Quad-major layout: lanes 4q..4q+3 hold one aligned 2x2 group.
+        const int q = t >> 2, k = t & 3;
+        const int lx = 2 * (q & 7) + (k & 1), ly = 2 * (q >> 3) + (k >> 1);
+        const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
+        px = ox + bx + lx;
+        py = oy + by + ly;
+        sx = float(bx + lx) + 0.5f;
+        sy = float(by + ly) + 0.5f;
+    }
+    const bool inimg = px < V.W && py < V.H;
+
+    Accum acc;
+    acc.T = 1.f; acc.cr = 0.f; acc.cg = 0.f; acc.cb = 0.f;
+    acc.alive = inimg;
+    Window<W> win;
+    win.init();
+
+    const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
+    const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
+    float4(*st)[kStage] = stage[wv];
+    const float amax = kn.alpha_max, tmin = kn.t_min;
+
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBatch) {
+        if (__ballot(acc.alive) == 0ull) break;
+        const int nb = int(min(uint32_t(kBatch), rg.y - b0));
+        if (lane < nb) {
+            const uint32_t gid = gids[b0 + lane];
+            const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
+            const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
+            const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
+            // Mean offset relative to the tile origin, split so that the
+            // integer part is exact: (ox - x0i) - x0f.
+            const float ex = float(ox - int(p0.x)) - p0.z;
+            const float ey = float(oy - int(p0.y)) - p0.w;
+            st[lane][0] = make_float4(ex, ey, p1.x, p1.y);          // M00 M01
+            st[lane][1] = make_float4(p1.z, p1.w, p2.x, p2.y);      // M10 M11 a3x a3y
+            st[lane][2] = make_float4(p2.z, p2.w, p3.x, p3.y);      // l2s kap n0 nx
+            st[lane][3] = make_float4(p3.z, p4.x, p4.y, p4.z);      // ny w0
+            st[lane][4] = make_float4(p4.w, p5.x, p5.y, p5.z);      // wx wy.x
+            st[lane][5] = make_float4(p5.w, p6.x, p6.y, p6.z);      // wy.yz r g
+            st[lane][6] = make_float4(p6.w, 0.f, 0.f, 0.f);         // b
+        }
+        wave_sync_lds();
+        for (int j = 0; j < nb; ++j) {
+            const float4 f0 = st[j][0], f1 = st[j][1], f2 = st[j][2];
+            const float dx = f0.x + sx, dy = f0.y + sy;
+            const float z1 = fmaf(f0.z, dx, f0.w * dy);
+            const float z2 = fmaf(f1.x, dx, f1.y * dy);
+            const float h = fmaf(f1.z, dx, fmaf(f1.w, dy, 1.f));
+            const float q = fmaf(z1, z1, z2 * z2);
+            const float h2 = h * h;
+            const bool pass = acc.alive && (h > 0.f) && (q <= f2.y * h2);
+            if (__ballot(pass) != 0ull) {  // wave-uniform
+                const float4 f3 = st[j][3], f4 = st[j][4], f5 = st[j][5], f6 = st[j][6];
+                Slot x;
+                x.a = pass ? fminf(amax, exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2))) : 0.f;
+                const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
+                const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
+                const float w1 = fmaf(f4.y, dx, fmaf(f5.x, dy, f3.z));
+                const float w2 = fmaf(f4.z, dx, fmaf(f5.y, dy, f3.w));
+                const float den = fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
+                x.t = pass ? num * __builtin_amdgcn_rcpf(den) : -INFINITY;
+                x.r = f5.z; x.g = f5.w; x.b = f6.x;
+                const Slot e = win.push(x);
+                acc.blend(e.a, e.r, e.g, e.b, tmin);
+            }
+            if (__ballot(acc.alive) == 0ull) break;
+        }
+        wave_sync_lds();
+    }
+    // Flush the window in ascending depth order.
+#pragma unroll
+    for (int i = 0; i < W; ++i) acc.blend(win.a[i], win.r[i], win.g[i], win.b[i], tmin);
+
+    float o[4] = {acc.cr + acc.T * kn.bg[0], acc.cg + acc.T * kn.bg[1], acc.cb + acc.T * kn.bg[2], 1.f - acc.T};
+    float* dst = V.foveated ? V.pre : V.out;
+    const size_t plane = size_t(V.W) * size_t(V.H);
+    if (cls == VRS_CLASS_LOW) {
+        for (int c = 0; c < 4; ++c) {
+            float* pl = dst + c * plane;
+            for (int yy = 0; yy < 2; ++yy)
+                for (int xx = 0; xx < 2; ++xx)
+                    if (px + xx < V.W && py + yy < V.H) pl[size_t(py + yy) * V.W + px + xx] = o[c];
+        }
+        return;
+    }
+    if (cls == VRS_CLASS_HYBRID) {
+        // Continuous mask from the angle to the fovea-centre ray.
+        const float d0 = (float(px) + 0.5f - V.cx) / V.f, d1 = (float(py) + 0.5f - V.cy) / V.f;
+        const float cx_ = d1 * V.fdir[2] - V.fdir[1];
+        const float cy_ = V.fdir[0] - d0 * V.fdir[2];
+        const float cz_ = d0 * V.fdir[1] - d1 * V.fdir[0];
+        const float dotp = d0 * V.fdir[0] + d1 * V.fdir[1] + V.fdir[2];
+        const float e = atan2f(sqrtf(cx_ * cx_ + cy_ * cy_ + cz_ * cz_), dotp);
+        float wm = (V.rho * (1.f + V.band) - e) / (V.rho * V.band);
+        wm = fminf(fmaxf(wm, 0.f), 1.f);
+        // Mean of the aligned 2x2 group over its in-image pixels.
+        const float cnt0 = inimg ? 1.f : 0.f;
+        float cnt = cnt0 + __shfl_xor(cnt0, 1);
+        cnt = cnt + __shfl_xor(cnt, 2);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float mine = inimg ? o[c] : 0.f;
+            float s = mine + __shfl_xor(mine, 1);
+            s = s + __shfl_xor(s, 2);
+            o[c] = wm * o[c] + (1.f - wm) * (s / cnt);
+        }
+    }
+    if (inimg) {
+        const size_t off = size_t(py) * V.W + px;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dst[c * plane + off] = o[c];
+    }
+}
+
+// K7: LOW pixels of a foveated view take the 3x3 binomial blur of the
+// nearest-neighbour-upsampled image (coordinates clamped to the image); other
+// pixels are copied.
+__global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __restrict__ cls) {
+    const int x = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (x >= V.W || y >= V.H) return;
+    const size_t plane = size_t(V.W) * size_t(V.H);
+    const uint8_t c = cls[V.cls_off + size_t(y >> 4) * V.ntx16 + (x >> 4)];
+    const size_t off = size_t(y) * V.W + x;
+    if (c != VRS_CLASS_LOW) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) V.out[k * plane + off] = V.pre[k * plane + off];
+        return;
+    }
+    const int xs[3] = {max(x - 1, 0), x, min(x + 1, V.W - 1)};
+    const int ys[3] = {max(y - 1, 0), y, min(y + 1, V.H - 1)};
+    const float wk[3] = {1.f, 2.f, 1.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float* p = V.pre + k * plane;
+        float s = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float* row = p + size_t(ys[a]) * V.W;
+            s = fmaf(wk[a], fmaf(wk[0], row[xs[0]], fmaf(wk[1], row[xs[1]], wk[2] * row[xs[2]])), s);
+        }
+        V.out[k * plane + off] = s * (1.f / 16.f);
+    }
+}
+
+template <int W>
+static void launch_render_w(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
+                            const uint32_t* items, uint32_t n_items, const RenderViews& views, const Knobs& kn,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_render<W>, dim3(n_items), dim3(kRenderThreads), 0, s, proj, n_gauss, gids, ranges, items,
+                       views, kn);
+}
+
+bool window_supported(int w) {
+    switch (w) {
+        case 1: case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32: return true;
+        default: return false;
+    }
+}
+
+int launch_render(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
+                  const uint32_t* items, uint32_t n_items, const RenderViews& views, const Knobs& kn, int window,
+                  const uint8_t* cls, hipStream_t s) {
+    if (n_items > 0) {
+        switch (window) {
+            case 1: launch_render_w<1>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 2: launch_render_w<2>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 3: launch_render_w<3>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 4: launch_render_w<4>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 6: launch_render_w<6>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 8: launch_render_w<8>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 12: launch_render_w<12>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 16: launch_render_w<16>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 24: launch_render_w<24>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            case 32: launch_render_w<32>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
+            default: return VRS_ERR_UNSUPPORTED;
+        }
+        const int rc = launch_status(hipGetLastError());
+        if (rc != VRS_OK) return rc;
+    }
+    for (int v = 0; v < views.n; ++v) {
+        const RenderView& V = views.v[v];
+        if (!V.foveated) continue;
+        hipLaunchKernelGGL(k_compose, dim3((V.W + 15) / 16, (V.H + 15) / 16), dim3(256), 0, s, V, cls);
+    }
+    return launch_status(hipGetLastError());
+}
+
+}  // namespace vrs

@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP translation units of libvrs.
+// Kernels take compact per-view tables by value (kernel arguments stay well
+// under 4 KB for VRS_MAX_VIEWS views), so calls on different streams never
+// share mutable state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vrs.h"
+
+namespace vrs {
+
+constexpr int kRec = VRS_RECORD_FLOATS;
+
+// Record layout (floats) of one projected Gaussian in one view.  The render
+// kernel stages fields [4, 28) plus the tile-relative mean offset; the per-pair
+// arithmetic it needs is described next to each group.
+enum RecField : int {
+    R_X0I = 0, R_Y0I = 1,    // integer part of the mean's image point (pixels)
+    R_X0F = 2, R_Y0F = 3,    // fractional part in [0, 1)
+    R_M00 = 4, R_M01 = 5,    // z = M delta / h: whitened tangent-plane coords,
+    R_M10 = 6, R_M11 = 7,    //   scaled so that |z|^2 = log2(e) D^2 / 2
+    R_A3X = 8, R_A3Y = 9,    // h = 1 + a3 . delta  (> 0 iff the ray is in front)
+    R_L2S = 10,              // log2(opacity)
+    R_KAP = 11,              // log2(opacity) - log2(alpha_min): pass iff |z|^2 <= KAP
+    R_N0 = 12, R_NX = 13, R_NY = 14,  // depth numerator  n0 + nx dx + ny dy
+    R_SPARE0 = 15,
+    R_W0 = 16,               // depth denominator |w0 + dx wx + dy wy|^2 (w0: 16..18,
+    R_WX = 19, R_WY = 22,    //   wx: 19..21, wy: 22..24)
+    R_RGB = 25,              // colour 25..27
+    R_SIG = 28,              // opacity (float)
+    R_SPARE1 = 29, R_SPARE2 = 30, R_SPARE3 = 31,
+};
+
+struct GaussPtrs {
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* opac;
+    const float* sh;
+    int n;
+    int sh_degree;
+};
+
+// Geometry of one view for the per-Gaussian kernels.
+struct GeoView {
+    double f;
+    float R[9];
+    float t[3];
+    float cx, cy;
+    int W, H;
+    int T;        // sort tile size (16 or 32)
+    int ntx, nty; // sort grid
+    uint32_t tile_off;
+};
+
+struct GeoViews {
+    int n;
+    GeoView v[VRS_MAX_VIEWS];
+};
+
+struct Knobs {
+    float z_near, alpha_min, alpha_max, t_min, dilation;
+    float bg[3];
+};
+
+// Per-view data for the render and compose kernels.
+struct RenderView {
+    float* out;         // final rgba [4][H][W]
+    float* pre;         // pre-compose image (foveated views), else == out
+    float f, cx, cy;
+    float fdir[3];      // unit ray of the fovea centre (camera frame)
+    float rho, band;    // fovea radius (rad) and band fraction
+    int W, H;
+    int T;              // sort tile size (16 or 32)
+    int ntx;            // sort grid width
+    int ntx16;          // 16x16 subtile grid width (class map row)
+    uint32_t tile_off;
+    uint32_t cls_off;   // offset of this view's class map in the plan
+    int foveated;
+};
+
+struct RenderViews {
+    int n;
+    RenderView v[VRS_MAX_VIEWS];
+};
+
+struct FovView {  // FP64 class decision of one foveated view
+    double f, cx, cy;
+    double dc[3];      // fovea-centre ray (unnormalised)
+    double dcn;        // |dc|
+    double cos_low;    // LOW iff cos(e) <= cos_low at every pixel
+    double cos_high;   // HIGH iff cos(e) >= cos_high at every pixel
+    int all_low;       // rho <= 0
+    int W, H, ntx32, nty32, ntx16, nty16;
+    uint32_t cls_off;
+};
+
+// What the item builder needs of every view.
+struct ItemView {
+    int foveated;
+    int T;          // sort tile size
+    int ntx;        // sort grid width
+    int ntx16;      // class-map row length
+    int ntiles;     // sort-grid tiles of the view
+    int W, H;
+    uint32_t cls_off;
+};
+
+struct ItemViews {
+    int n;
+    ItemView v[VRS_MAX_VIEWS];
+};
+
+// Work items: view (5 bits) | class (2) | subtile (2) | sort-grid tile (23).
+__host__ __device__ inline uint32_t item_pack(int view, int cls, int sub, uint32_t tile) {
+    return (uint32_t(view) << 27) | (uint32_t(cls) << 25) | (uint32_t(sub) << 23) | tile;
+}
+__host__ __device__ inline int item_view(uint32_t it) { return int(it >> 27); }
+__host__ __device__ inline int item_class(uint32_t it) { return int((it >> 25) & 3u); }
+__host__ __device__ inline int item_sub(uint32_t it) { return int((it >> 23) & 3u); }
+__host__ __device__ inline uint32_t item_tile(uint32_t it) { return it & 0x7FFFFFu; }
+
+// Status helper: the first error written wins.
+__device__ inline void set_status(int* status, int code) {
+    if (status) atomicCAS(status, 0, code);
+}
+
+// Plan layout (bytes): [0, 4) item count, [256, 256 + 4 * items_max) items,
+// then the u8 class maps of all views (16x16 subtile grids).
+constexpr size_t kPlanItemsOff = 256;
+
+// Launch helpers (host).
+int launch_status(hipError_t e);
+
+}  // namespace vrs

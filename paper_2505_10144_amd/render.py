@@ -1,0 +1,204 @@
+"""Torch glue over the C ABI: device buffers and streams come from PyTorch,
+every computation runs in libvrs's HIP kernels.
+
+Typical use::
+
+    r = Renderer(cams, foveas, params, n_gaussians)
+    g = r.upload(scene)               # SoA float32 tensors on the GPU
+    images = r.render(g)              # list of (4, H, W) float32 tensors
+
+``Renderer`` owns every buffer of one configuration (cameras, foveae, knobs,
+Gaussian count), builds the foveation plan once (the paper precomputes the
+tile mapping per eye and reuses it across frames, Sec. 4.3) and sizes the
+instance buffers from an exact count on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Gaussians:
+    """Device-resident Gaussian parameters in the library's SoA layout."""
+
+    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree=3):
+        self.means = means.contiguous()
+        self.log_scales = log_scales.contiguous()
+        self.quats = quats.contiguous()
+        self.opacity_logits = opacity_logits.contiguous()
+        self.sh = sh.contiguous()
+        self.sh_degree = int(sh_degree)
+        for t in (self.means, self.log_scales, self.quats, self.opacity_logits, self.sh):
+            if t.dtype != torch.float32 or not t.is_cuda:
+                raise ValueError("Gaussian parameters must be float32 CUDA tensors")
+
+    @property
+    def n(self):
+        return int(self.means.shape[1])
+
+    def struct(self) -> L.vrs_gaussians:
+        g = L.vrs_gaussians()
+        g.n = self.n
+        g.sh_degree = self.sh_degree
+        g.means = self.means.data_ptr()
+        g.log_scales = self.log_scales.data_ptr()
+        g.quats = self.quats.data_ptr()
+        g.opacity_logits = self.opacity_logits.data_ptr()
+        g.sh = self.sh.data_ptr()
+        return g
+
+
+def upload(scene, device="cuda") -> Gaussians:
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+    return Gaussians(t(scene.means), t(scene.log_scales), t(scene.quats),
+                     t(scene.opacity_logits), t(scene.sh), scene.sh_degree)
+
+
+class Renderer:
+    def __init__(self, cams: Sequence, foveas, params, n: int, device="cuda",
+                 capacity: Optional[int] = None, stream=None):
+        if not isinstance(foveas, (list, tuple)):
+            foveas = [foveas] * len(cams)
+        if len(cams) != len(foveas):
+            raise ValueError("one fovea per camera")
+        self.cams, self.foveas, self.params = list(cams), list(foveas), params
+        self.n = int(n)
+        self.device = torch.device(device)
+        self.stream = stream
+        self.c_cams = L.camera_array(self.cams)
+        self.c_fovs = L.fovea_array(self.foveas)
+        self.c_params = L.make_params(params)
+        self.V = len(self.cams)
+        sizes = self._sizes(0)
+        self.tiles_total = sizes.tiles_total
+        dev = self.device
+        u8 = lambda nbytes: torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+        self.proj = u8(sizes.proj_bytes)
+        self.counts = torch.empty(max(self.V * self.n, 1), dtype=torch.int32, device=dev)
+        self.ranges = torch.empty(max(2 * self.tiles_total, 2), dtype=torch.int32, device=dev)
+        self.n_inst = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.plan = u8(sizes.plan_bytes)
+        self.render_ws = u8(sizes.render_ws_bytes)
+        self.images = [torch.empty((4, c.height, c.width), dtype=torch.float32, device=dev)
+                       for c in self.cams]
+        self._img_ptrs = (ctypes.c_void_p * self.V)(*[im.data_ptr() for im in self.images])
+        self.capacity = 0
+        self.keys = self.gids = self.sort_ws = None
+        if capacity is not None:
+            self._alloc_instances(int(capacity))
+        n_items = ctypes.c_uint32(0)
+        L.call("vrs_fovea_plan", self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params),
+               _ptr(self.plan), ctypes.c_size_t(self.plan.numel()), ctypes.byref(n_items),
+               _stream(self.stream))
+        self.n_items = int(n_items.value)
+        self.items_max = sizes.items_max
+
+    # -- sizes / buffers --------------------------------------------------------
+    def _sizes(self, capacity):
+        s = L.vrs_sizes()
+        L.call("vrs_workspace_size", self.n, self.c_cams, self.c_fovs, self.V,
+               ctypes.byref(self.c_params), ctypes.c_size_t(capacity), ctypes.byref(s))
+        return s
+
+    def _alloc_instances(self, capacity):
+        s = self._sizes(capacity)
+        self.capacity = capacity
+        dev = self.device
+        self.keys = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+        self.gids = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        self.sort_ws = torch.empty(max(int(s.sort_ws_bytes), 256), dtype=torch.uint8, device=dev)
+
+    def ensure_capacity(self, g: Gaussians, headroom=1.25):
+        """Exact instance count of the current scene/cameras (one sync), and
+        instance buffers of at least that size times ``headroom``."""
+        if self.sort_ws is None:
+            self._alloc_instances(0)
+        self.preprocess(g)
+        self.status.zero_()
+        L.call("vrs_duplicate", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
+               ctypes.byref(self.c_params), _ptr(self.counts), _ptr(self.keys), _ptr(self.gids),
+               ctypes.c_size_t(0), _ptr(self.n_inst), _ptr(self.sort_ws),
+               ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status), _stream(self.stream))
+        need = int(self.n_inst.item())
+        if need > self.capacity:
+            self._alloc_instances(max(int(need * headroom), 1024))
+        self.status.zero_()
+        return need
+
+    # -- stages -------------------------------------------------------------------
+    def preprocess(self, g: Gaussians):
+        L.call("vrs_preprocess", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
+               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.status),
+               _stream(self.stream))
+
+    def duplicate(self, g: Gaussians):
+        L.call("vrs_duplicate", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
+               ctypes.byref(self.c_params), _ptr(self.counts), _ptr(self.keys), _ptr(self.gids),
+               ctypes.c_size_t(self.capacity), _ptr(self.n_inst), _ptr(self.sort_ws),
+               ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status), _stream(self.stream))
+
+    def key_bits(self):
+        b = 0
+        while (1 << b) < self.tiles_total:
+            b += 1
+        return 32 + b
+
+    def sort(self, g: Gaussians):
+        L.call("vrs_sort", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
+               ctypes.byref(self.c_params), _ptr(self.counts), _ptr(self.keys), _ptr(self.gids),
+               ctypes.c_size_t(self.capacity), _ptr(self.n_inst), _ptr(self.ranges),
+               _ptr(self.sort_ws), ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status),
+               _stream(self.stream))
+
+    def blend(self):
+        L.call("vrs_render_foveated", _ptr(self.proj), self.n, _ptr(self.gids), _ptr(self.ranges),
+               self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), _ptr(self.plan),
+               ctypes.c_uint32(self.n_items), self._img_ptrs, _ptr(self.render_ws),
+               ctypes.c_size_t(self.render_ws.numel()), _ptr(self.status), _stream(self.stream))
+
+    def render(self, g: Gaussians) -> List[torch.Tensor]:
+        """One frame for every view: preprocess, sort, blend (and compose)."""
+        if g.n != self.n:
+            raise ValueError("Gaussian count differs from the renderer's")
+        if self.sort_ws is None:
+            self.ensure_capacity(g)
+        self.preprocess(g)
+        self.sort(g)
+        self.blend()
+        return self.images
+
+    def check(self):
+        """Synchronise and raise if the device reported an error (capacity)."""
+        st = int(self.status.item())
+        if st != L.VRS_OK:
+            raise L.VrsError("device", st)
+        return int(self.n_inst.item())
+
+    # -- views of the plan, for tests and tools -----------------------------------
+    def plan_items(self) -> np.ndarray:
+        off = L.PLAN_ITEMS_OFFSET
+        raw = self.plan[off:off + 4 * self.n_items].cpu().numpy().view(np.uint32)
+        return raw.copy()
+
+    def plan_classes(self) -> bytes:
+        off = L.PLAN_ITEMS_OFFSET + 4 * self.items_max
+        return self.plan[off:].cpu().numpy()
+
+    def records(self) -> torch.Tensor:
+        return self.proj[: self.V * self.n * L.VRS_RECORD_FLOATS * 4].view(torch.float32).view(
+            self.V, self.n, L.VRS_RECORD_FLOATS)

@@ -38,7 +38,7 @@ class Params:
     performance knob that never changes the output)."""
     tile: int = 16
     window: int = 16
-    blend_batch: int = 128
+    blend_batch: int = 64
     z_near: float = float(F32(0.2))
     alpha_min: float = float(F32(1.0 / 255.0))
     alpha_max: float = float(F32(0.99))

@@ -1,0 +1,341 @@
+"""GPU parity: every stage of the HIP path, called through the C ABI, against
+the FP64 oracle on the same seeded inputs.
+
+Bars: bit-exact for the foveation classes, the sort and the tile ranges;
+instance sets equal except oracle-flagged borderline instances, key depths
+within one float32 ulp; images within 2e-4 max-abs per channel on every pixel
+the oracle does not flag as borderline (see oracle.render for the flags)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import fovea as ofov
+from oracle import tiles as otiles
+from oracle.render import OracleOptions
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2505_10144_amd import render
+    from paper_2505_10144_amd import _lib
+    _lib.load()
+    return render
+
+
+def run_gpu(R, scene, cams, foveas, params):
+    print(f"[gpu] n={scene.n} views={len(cams)} size={cams[0].width}x{cams[0].height} "
+          f"tile={params.tile} W={params.window}", flush=True)
+    r = R.Renderer(cams, foveas, params, scene.n)
+    g = R.upload(scene)
+    imgs = r.render(g)
+    torch.cuda.synchronize()
+    r.check()
+    return r, g, [im.cpu().numpy().astype(np.float64) for im in imgs]
+
+
+def compare(imgs, ref, tol=TOL, max_flag_frac=0.05):
+    worst, flagged = 0.0, 0
+    total = 0
+    for v, got in enumerate(imgs):
+        assert np.all(np.isfinite(got)), "non-finite output"
+        valid = ref["valid"][v]
+        ok = valid & ~ref["flags"][v]
+        err = np.abs(got - ref["images"][v])
+        if ok.any():
+            e = err[:, ok]
+            worst = max(worst, float(e.max()))
+            if e.max() > tol:
+                idx = np.argwhere((err > tol).any(axis=0) & ok)[:5]
+                raise AssertionError(f"view {v}: max err {e.max():.3e} at {idx.tolist()}; "
+                                     f"got {got[:, idx[0][0], idx[0][1]]} want "
+                                     f"{ref['images'][v][:, idx[0][0], idx[0][1]]}")
+        flagged += int((valid & ref["flags"][v]).sum())
+        total += int(valid.sum())
+    frac = flagged / max(total, 1)
+    print(f"[parity] max err {worst:.3e}, flagged {flagged}/{total} ({frac:.2e})", flush=True)
+    assert frac <= max_flag_frac
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# Images
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tiny_plain_full_image(R, seed):
+    scene, cams, fov, params = synth.config_tiny(seed)
+    _, _, imgs = run_gpu(R, scene, cams, [fov], params)
+    ref = oracle.render(scene, cams, fov, params)
+    compare(imgs, ref)
+
+
+@pytest.mark.parametrize("W", [1, 4, 8, 32])
+def test_window_lengths(R, W):
+    scene, cams, fov, params = synth.config_tiny(2, n=4000, size=96, window=W)
+    _, _, imgs = run_gpu(R, scene, cams, [fov], params)
+    ref = oracle.render(scene, cams, fov, params)
+    compare(imgs, ref)
+
+
+@pytest.mark.parametrize("size", [(250, 170), (33, 47), (1, 1), (17, 16)])
+def test_ragged_image_sizes(R, size):
+    w, h = size
+    scene = synth.uniform_scene(3, 3000, log_scale=(-3.5, 0.5))
+    cam = synth.camera_translate((0.05, -0.02, -3.0), 80.0, w, h)
+    params = synth.default_params(tile=16, window=8)
+    _, _, imgs = run_gpu(R, scene, [cam], [synth.fovea_off()], params)
+    ref = oracle.render(scene, [cam], synth.fovea_off(), params)
+    compare(imgs, ref)
+
+
+def test_plain_view_with_32_tiles(R):
+    scene = synth.uniform_scene(4, 3000, log_scale=(-3.5, 0.5))
+    cam = synth.camera_translate((0.0, 0.0, -3.0), 90.0, 120, 88)
+    params = synth.default_params(tile=32, window=12)
+    _, _, imgs = run_gpu(R, scene, [cam], [synth.fovea_off()], params)
+    ref = oracle.render(scene, [cam], synth.fovea_off(), params)
+    compare(imgs, ref)
+
+
+@pytest.mark.parametrize("seed,radius", [(0, 12.0), (1, 20.0)])
+def test_foveated_stereo_small(R, seed, radius):
+    scene, cams, fovs, params = synth.config_stereo(seed, n=6000, width=224, height=192, radius_deg=radius)
+    _, _, imgs = run_gpu(R, scene, cams, fovs, params)
+    ref = oracle.render(scene, cams, fovs, params)
+    assert any((c[1] == ofov.HYBRID).any() for c in ref["classes"])
+    assert any((c[1] == ofov.LOW).any() for c in ref["classes"])
+    compare(imgs, ref)
+
+
+def test_foveated_ragged_and_offcentre(R):
+    scene = synth.cluster_scene(5, 8000, log_scale=(-4.5, 0.6))
+    cam = synth.camera_translate((0.0, 0.0, -3.0), 100.0, 203, 141)
+    fov = synth.Fovea(True, (71.3, 88.9), 14.0, 0.25)
+    params = synth.default_params(tile=32, window=16)
+    _, _, imgs = run_gpu(R, scene, [cam], [fov], params)
+    ref = oracle.render(scene, [cam], fov, params)
+    compare(imgs, ref)
+
+
+def test_empty_and_all_culled(R):
+    cam = synth.camera_translate((0, 0, -3), 90, 64, 48)
+    params = synth.default_params(tile=16, window=4)
+    # All Gaussians behind the camera: every count is zero.
+    scene = synth.uniform_scene(6, 500)
+    scene.means[2] = -10.0
+    _, _, imgs = run_gpu(R, scene, [cam], [synth.fovea_off()], params)
+    assert np.all(imgs[0][3] == 0.0) and np.all(imgs[0][:3] == 0.0)
+    # Opacity below alpha_min everywhere.
+    scene2 = synth.uniform_scene(7, 500)
+    scene2.opacity_logits[:] = -20.0
+    _, _, imgs = run_gpu(R, scene2, [cam], [synth.fovea_off()], params)
+    assert np.all(imgs[0] == 0.0)
+
+
+def test_background_colour(R):
+    scene, cams, fov, params = synth.config_tiny(8, n=2000, size=64)
+    params = params.replace(background=(0.25, 0.5, 1.0))
+    _, _, imgs = run_gpu(R, scene, cams, [fov], params)
+    ref = oracle.render(scene, cams, fov, params)
+    compare(imgs, ref)
+
+
+def test_deterministic_repeat(R):
+    scene, cams, fovs, params = synth.config_stereo(2, n=20000, width=320, height=288)
+    r, g, a = run_gpu(R, scene, cams, fovs, params)
+    b = [im.cpu().numpy() for im in r.render(g)]
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert np.array_equal(x.astype(np.float32), y)
+
+
+# ---------------------------------------------------------------------------
+# Stages
+# ---------------------------------------------------------------------------
+
+def test_fovea_plan_classes_bit_exact(R):
+    scene, cams, fovs, params = synth.config_stereo(0, n=10, width=400, height=352, radius_deg=18.0)
+    fovs[1] = synth.Fovea(True, (130.0, 201.0), 10.0, 0.3)
+    r = R.Renderer(cams, fovs, params, scene.n)
+    cls = r.plan_classes()
+    items = r.plan_items()
+    off = 0
+    n_items = 0
+    for v, cam in enumerate(cams):
+        split, sub, _ = ofov.classify(cam, fovs[v])
+        m = cls[off:off + sub.size].reshape(sub.shape).astype(np.int16)
+        m[m == 255] = -1
+        assert np.array_equal(m, sub.astype(np.int16)), f"view {v}"
+        off += sub.size
+        n_items += int((~split).sum()) + int(((sub >= 0) & np.repeat(np.repeat(split, 2, 0), 2, 1)).sum())
+    assert r.n_items == n_items == len(items)
+    # Items cover every in-image pixel exactly once.
+    for v, cam in enumerate(cams):
+        cover = np.zeros((cam.height, cam.width), np.int32)
+        for it in items[(items >> 27) == v]:
+            cl, s, t = (it >> 25) & 3, (it >> 23) & 3, it & 0x7FFFFF
+            ntx = -(-cam.width // 32)
+            tx, ty = t % ntx, t // ntx
+            if cl == 0:
+                cover[ty * 32:ty * 32 + 32, tx * 32:tx * 32 + 32] += 1
+            else:
+                x0, y0 = tx * 32 + (s & 1) * 16, ty * 32 + (s >> 1) * 16
+                cover[y0:y0 + 16, x0:x0 + 16] += 1
+        assert np.all(cover == 1)
+
+
+def _stage_setup(R, scene, cams, fovs, params):
+    r = R.Renderer(cams, fovs, params, scene.n)
+    g = R.upload(scene)
+    r.ensure_capacity(g)
+    r.preprocess(g)
+    r.duplicate(g)
+    torch.cuda.synchronize()
+    r.check()
+    return r, g
+
+
+def test_instances_and_keys_match_oracle(R):
+    scene, cams, fovs, params = synth.config_stereo(3, n=8000, width=256, height=224)
+    r, g = _stage_setup(R, scene, cams, fovs, params)
+    n = int(r.n_inst.item())
+    keys = r.keys[:n].cpu().numpy().view(np.uint64)
+    gids = r.gids[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    ref = oracle.render(scene, cams, fovs, params, OracleOptions(shade=False))
+    assert int(ref["inst_border"].sum()) == 0
+    assert len(ref["gids"]) == n
+    s32 = np.uint64(32)
+    gpu = {(int(k >> s32), int(gg)): int(k & np.uint64(0xFFFFFFFF)) for k, gg in zip(keys, gids)}
+    ora = {(int(k >> s32), int(gg)): int(k & np.uint64(0xFFFFFFFF)) for k, gg in zip(ref["keys"], ref["gids"])}
+    assert gpu.keys() == ora.keys()
+    diffs = np.array([abs(gpu[k] - ora[k]) for k in ora])
+    print(f"[keys] {len(diffs)} instances, {int((diffs > 0).sum())} differ by one ulp", flush=True)
+    assert diffs.max() <= 1
+    assert (diffs > 0).mean() < 1e-3
+    # Instances are written in (view, Gaussian, tile) order.
+    order = np.lexsort((keys >> s32, gids))
+    view = (keys >> s32).astype(np.int64) >= ref["view_offsets"][1]
+    assert np.all(np.diff(view.astype(np.int64)) >= 0)
+    # Per-(view, Gaussian) counts equal the oracle's.
+    cnt = r.counts[: 2 * scene.n].cpu().numpy().reshape(2, scene.n)
+    otile = (ref["keys"] >> s32).astype(np.int64)
+    for v in range(2):
+        inview = (otile >= ref["view_offsets"][v]) & (otile < ref["view_offsets"][v] + ref["grids"][v].n)
+        oc = np.bincount(ref["gids"][inview].astype(np.int64), minlength=scene.n)
+        assert np.array_equal(cnt[v], oc)
+
+
+def test_sort_pairs_bit_exact_on_gpu_keys(R):
+    from paper_2505_10144_amd import _lib as L
+    import ctypes
+    scene, cams, fovs, params = synth.config_stereo(4, n=20000, width=384, height=320)
+    r, g = _stage_setup(R, scene, cams, fovs, params)
+    n = int(r.n_inst.item())
+    k0 = r.keys[:n].cpu().numpy().view(np.uint64).copy()
+    v0 = r.gids[:n].cpu().numpy().view(np.uint32).copy()
+    L.call("vrs_sort_pairs", ctypes.c_void_p(r.keys.data_ptr()), ctypes.c_void_p(r.gids.data_ptr()),
+           ctypes.c_void_p(r.n_inst.data_ptr()), ctypes.c_size_t(r.capacity), r.key_bits(),
+           ctypes.c_void_p(r.sort_ws.data_ptr()), ctypes.c_size_t(r.sort_ws.numel()),
+           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    ks = r.keys[:n].cpu().numpy().view(np.uint64)
+    vs = r.gids[:n].cpu().numpy().view(np.uint32)
+    order = np.lexsort((v0, k0))
+    assert np.array_equal(ks, k0[order]) and np.array_equal(vs, v0[order])
+    # Ranges from the sorted keys equal the oracle's scan of the same keys.
+    L.call("vrs_tile_ranges", ctypes.c_void_p(r.keys.data_ptr()), ctypes.c_void_p(r.n_inst.data_ptr()),
+           ctypes.c_size_t(r.capacity), ctypes.c_uint32(r.tiles_total), ctypes.c_void_p(r.ranges.data_ptr()),
+           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    rg = r.ranges[: 2 * r.tiles_total].cpu().numpy().view(np.uint32).reshape(-1, 2)
+    assert np.array_equal(rg, otiles.tile_ranges(ks, r.tiles_total))
+
+
+@pytest.mark.parametrize("n,bits,dups", [(0, 40, 1), (1, 40, 1), (4095, 64, 1), (4097, 33, 7),
+                                         (100_003, 46, 50), (300_000, 64, 1000)])
+def test_sort_pairs_random(R, n, bits, dups):
+    from paper_2505_10144_amd import _lib as L
+    import ctypes
+    rng = np.random.default_rng(n + bits)
+    print(f"[sort] n={n} bits={bits}", flush=True)
+    hi = (1 << bits) - 1 if bits < 64 else (1 << 64) - 1
+    base = rng.integers(0, hi, size=max(n // dups, 1), dtype=np.uint64, endpoint=True) if n else np.zeros(0, np.uint64)
+    keys = base[rng.integers(0, len(base), size=n)] if n else np.zeros(0, np.uint64)
+    vals = rng.permutation(n).astype(np.uint32)
+    cap = n + 123
+    kt = torch.zeros(cap, dtype=torch.int64, device="cuda")
+    vt = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    if n:
+        kt[:n] = torch.from_numpy(keys.view(np.int64)).cuda()
+        vt[:n] = torch.from_numpy(vals.view(np.int32)).cuda()
+    nt = torch.tensor([n], dtype=torch.int32, device="cuda")
+    ws = torch.empty(int(L.load().vrs_sort_pairs_workspace_size(cap)), dtype=torch.uint8, device="cuda")
+    L.call("vrs_sort_pairs", ctypes.c_void_p(kt.data_ptr()), ctypes.c_void_p(vt.data_ptr()),
+           ctypes.c_void_p(nt.data_ptr()), ctypes.c_size_t(cap), bits, ctypes.c_void_p(ws.data_ptr()),
+           ctypes.c_size_t(ws.numel()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    ks = kt[:n].cpu().numpy().view(np.uint64)
+    vs = vt[:n].cpu().numpy().view(np.uint32)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(ks, keys[order]) and np.array_equal(vs, vals[order])
+    assert np.all(kt[n:].cpu().numpy() == 0)
+
+
+def test_capacity_overflow_is_reported_and_recoverable(R):
+    from paper_2505_10144_amd import _lib as L
+    scene, cams, fovs, params = synth.config_stereo(5, n=5000, width=192, height=160)
+    r = R.Renderer(cams, fovs, params, scene.n, capacity=64)
+    g = R.upload(scene)
+    r.status.zero_()
+    r.preprocess(g)
+    r.sort(g)
+    torch.cuda.synchronize()
+    assert int(r.status.item()) == L.VRS_ERR_CAPACITY
+    need = int(r.n_inst.item())
+    assert need > 64 and r.keys.numel() == 64
+    with pytest.raises(L.VrsError):
+        r.check()
+    r2 = R.Renderer(cams, fovs, params, scene.n, capacity=need)
+    r2.render(g)
+    torch.cuda.synchronize()
+    assert r2.check() == need
+
+
+def test_record_colours_and_alpha(R):
+    """K1 records: colour equals the oracle's SH colour, and alpha evaluated
+    from the record formula at the mean's pixel equals the oracle's."""
+    scene, cams, fovs, params = synth.config_stereo(6, n=3000, width=256, height=224)
+    r, g = _stage_setup(R, scene, cams, fovs, params)
+    rec = r.records().cpu().numpy().astype(np.float64)
+    from oracle.render import preprocess_view
+    for v, cam in enumerate(cams):
+        pre = preprocess_view(scene, cam, params)
+        ok = pre["valid"]
+        np.testing.assert_allclose(rec[v, ok, 25:28], pre["color"][ok], atol=2e-6)
+        x0 = rec[v, ok, 0] + rec[v, ok, 2]
+        y0 = rec[v, ok, 1] + rec[v, ok, 3]
+        np.testing.assert_allclose(x0, pre["x0"][ok], atol=1e-4, rtol=1e-6)
+        np.testing.assert_allclose(y0, pre["y0"][ok], atol=1e-4, rtol=1e-6)
+        np.testing.assert_allclose(np.exp2(rec[v, ok, 10]), pre["sigma"][ok], rtol=1e-6)
+
+
+def test_stereo_full_size_sampled_tiles(R):
+    """The full 500k-Gaussian stereo workload at 2064x2208 per eye, in the
+    launch configuration of the benchmark, checked on sampled tiles (plus the
+    fovea) against the oracle."""
+    scene, cams, fovs, params = synth.config_stereo(0)
+    r, g, imgs = run_gpu(R, scene, cams, fovs, params)
+    rng = np.random.default_rng(1)
+    grid = otiles.TileGrid(cams[0].width, cams[0].height, 32)
+    centre = (grid.nty // 2) * grid.ntx + grid.ntx // 2
+    sel = {v: sorted(set(rng.choice(grid.n, 6, replace=False).tolist() + [centre, centre + 1])) for v in range(2)}
+    ref = oracle.render(scene, cams, fovs, params, OracleOptions(tiles=sel, workers=8))
+    compare(imgs, ref, max_flag_frac=0.25)
