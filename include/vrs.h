@@ -124,12 +124,14 @@ typedef struct {
 
 /* Buffer sizes for one configuration (all bytes unless noted). */
 typedef struct {
-    size_t proj_bytes;       /* records: n_views * n * VRS_RECORD_FLOATS floats   */
+    size_t proj_bytes;       /* per view and Gaussian: a 128-byte FP32 render record
+                                ([n_views][n][32] floats) followed, after all of them,
+                                by a 224-byte FP64 tile-test record                  */
     size_t counts_bytes;     /* uint32 counts[n_views][n]                         */
     uint32_t tiles_total;    /* sum over views of sort-grid tiles (ranges rows)    */
     uint32_t items_max;      /* upper bound on render work items                   */
     size_t plan_bytes;       /* work list + per-view subtile class maps            */
-    size_t sort_ws_bytes;    /* vrs_sort workspace for `capacity` instances        */
+    size_t sort_ws_bytes;    /* vrs_duplicate/vrs_sort workspace for `capacity`    */
     size_t render_ws_bytes;  /* vrs_render_foveated workspace (pre-compose images) */
 } vrs_sizes;
 
@@ -155,27 +157,33 @@ int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_vi
 
 /* Per-Gaussian preprocessing (Sec. 3 Eq. 1, Optimal Projection of Sec. 3 end
  * and Sec. 4.2, SH colour; one thread per Gaussian covering every view).
- * Writes per view and Gaussian a record of VRS_RECORD_FLOATS floats into
- * `proj` ([n_views][n][32], 128-byte aligned rows) and the exact number of
- * tiles that survive the tangent-plane tile test (Eq. 4) into
- * counts[n_views][n] (0 for culled Gaussians: camera z <= z_near, opacity <
- * alpha_min, non-finite parameters).  Sort grids: 32x32 for foveated views,
- * p->tile (16) otherwise. */
+ * Writes into `proj` (proj_bytes, 16-byte aligned) each Gaussian's FP32
+ * render record per view -- rows [n_views][n][VRS_RECORD_FLOATS] -- and its
+ * FP64 tile-test record, and into counts[n_views][n] the number of candidate
+ * tiles: the tiles meeting the image of the cone of directions in which the
+ * splat can reach alpha_min (a conservative bound; the exact tile test of
+ * Eq. 4 runs in vrs_duplicate).  Culled Gaussians (camera z <= z_near,
+ * opacity < alpha_min, non-finite parameters) get 0.  Sort grids: 32x32 for
+ * foveated views, p->tile otherwise. */
 int vrs_preprocess(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
                    int32_t n_views, const vrs_params* p, void* proj, uint32_t* counts,
                    int32_t* status_dev, vrs_stream_t stream);
 
 /* Gaussian/tile instantiation (Sec. 3 tile binning; Eq. 4 culling; per-tile
  * depth at the back-projected maximum point, Sec. 4.2).  Exclusive scan of
- * counts, then for each surviving (Gaussian, tile) pair writes
- *   keys[i] = (global_tile << 32) | ord(float32(depth)),  gids[i] = Gaussian
- * in (view, Gaussian, tile) order, where global_tile = view offset + ty*ntx +
- * tx and ord maps float order to unsigned order.  *n_inst_dev receives the
- * total.  If it exceeds `capacity`, *status_dev = VRS_ERR_CAPACITY, only the
- * first `capacity` pairs are written and *n_inst_dev still holds the
- * required count.  `ws` must hold sort_ws_bytes. */
+ * the candidate counts, then one thread per candidate (Gaussian, tile) runs
+ * the exact tangent-plane tile test in FP64 and writes, at the candidate's
+ * slot (order: view, Gaussian, tile),
+ *   keys[c] = (global_tile << 32) | ord(float32(depth)),  gids[c] = Gaussian
+ * for a kept instance, or keys[c] = UINT64_MAX (dead) for a culled one;
+ * global_tile = view offset + ty*ntx + tx and ord maps float order to
+ * unsigned order.  n_inst_dev[0] receives the number of candidates (the
+ * capacity needed) and n_inst_dev[1] the number of kept instances.  If the
+ * candidates exceed `capacity`, *status_dev = VRS_ERR_CAPACITY and only the
+ * first `capacity` slots are written.  `proj`/`counts` come from
+ * vrs_preprocess; `ws` must hold sort_ws_bytes. */
 int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
-                  int32_t n_views, const vrs_params* p, const uint32_t* counts,
+                  int32_t n_views, const vrs_params* p, const void* proj, const uint32_t* counts,
                   uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev,
                   void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream);
 
@@ -193,9 +201,11 @@ size_t vrs_sort_pairs_workspace_size(size_t capacity);
 int vrs_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity,
                     uint32_t tiles_total, uint32_t* ranges, vrs_stream_t stream);
 
-/* vrs_duplicate + vrs_sort_pairs + vrs_tile_ranges. */
+/* vrs_duplicate, then the radix sort by (key, gid) whose first pass drops the
+ * dead keys, so the first n_inst_dev[1] entries of keys/gids are the sorted
+ * instances, then vrs_tile_ranges over them. */
 int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
-             int32_t n_views, const vrs_params* p, const uint32_t* counts,
+             int32_t n_views, const vrs_params* p, const void* proj, const uint32_t* counts,
              uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev,
              uint32_t* ranges, void* ws, size_t ws_bytes, int32_t* status_dev,
              vrs_stream_t stream);
@@ -214,6 +224,31 @@ int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const
                         const vrs_params* p, const void* plan, uint32_t n_items,
                         float* const* rgba, void* ws, size_t ws_bytes,
                         int32_t* status_dev, vrs_stream_t stream);
+
+/* The two halves of vrs_render_foveated, for callers that time or schedule
+ * them separately: vrs_blend runs the single-launch per-tile blending (LOW
+ * items write their 2x2 groups, foveated views write into `ws`, plain views
+ * straight into rgba); vrs_compose then writes the final image of every
+ * foveated view from `ws` (nothing to do for plain views). */
+int vrs_blend(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
+              const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+              const vrs_params* p, const void* plan, uint32_t n_items,
+              float* const* rgba, void* ws, size_t ws_bytes, int32_t* status_dev,
+              vrs_stream_t stream);
+int vrs_compose(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                const vrs_params* p, const void* plan, float* const* rgba, void* ws,
+                size_t ws_bytes, vrs_stream_t stream);
+
+/* Instrumented vrs_blend (same output) that also adds to counters_dev[5]
+ * (uint64, caller-zeroed): [0] evaluated (sample, list entry) pairs, [1]
+ * pairs whose alpha reaches alpha_min, [2] in-image samples, [3] samples
+ * stopped by t_min, [4] list entries staged by the waves.  These are the
+ * work units of the blending roofline; it runs slower than vrs_blend. */
+int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
+                    const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                    const vrs_params* p, const void* plan, uint32_t n_items,
+                    float* const* rgba, void* ws, size_t ws_bytes, uint64_t* counters_dev,
+                    vrs_stream_t stream);
 
 /* Human-readable name of a status code. */
 const char* vrs_status_string(int code);

@@ -27,6 +27,7 @@ import dataclasses
 import math
 import multiprocessing as mp
 import os
+import time
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -210,6 +211,7 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
     if not isinstance(foveas, (list, tuple)):
         foveas = [foveas] * len(cams)
     V = len(cams)
+    t_start = time.perf_counter()
     pres, grids, insts, offs = [], [], [], []
     off = 0
     for v, cam in enumerate(cams):
@@ -259,10 +261,12 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
             d[int(gt - lo)] = (sgids[s:e], amb_next[s:e])
         lists.append(d)
 
+    t_keys = time.perf_counter() - t_start
     if not opts.shade:
         return dict(pre=pres, grids=grids, view_offsets=offs, n_tiles=off, inst_tile=all_tile,
                     inst_gid=all_gid, inst_depth=all_dep, inst_border=all_border, keys=skeys,
-                    gids=sgids, depths=sdep, ranges=ranges, stats=dict(n_inst=int(len(skeys))))
+                    gids=sgids, depths=sdep, ranges=ranges,
+                    stats=dict(n_inst=int(len(skeys)), t_keys=t_keys))
     # Step 4: shading jobs.
     jobs = []
     classes = []
@@ -288,6 +292,7 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
                 jobs.append((v, "plain", t, -1))
 
     global _WORK
+    t_shade0 = time.perf_counter()
     _WORK = dict(cams=cams, pre=pres, params=params, opts=opts, grids=grids, lists=lists)
     if opts.workers > 1 and len(jobs) > 1:
         ctx = mp.get_context("fork")
@@ -296,10 +301,12 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
     else:
         results = [_shade_job(j) for j in jobs]
     _WORK = {}
+    t_shade = time.perf_counter() - t_shade0
 
     # Step 5: assemble and compose.
     images, flagged, shaded = [], [], []
-    stats = dict(pairs=0, contrib=0, stopped=0, samples=0)
+    stats = dict(pairs=0, contrib=0, stopped=0, samples=0, jobs=len(jobs), t_keys=t_keys,
+                 t_shade=t_shade)
     recs = {}
     for v, cam in enumerate(cams):
         images.append(np.full((4, cam.height, cam.width), np.nan))

@@ -71,17 +71,24 @@ SIGNATURES = {
     "vrs_preprocess": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
                             ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P]),
     "vrs_duplicate": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
-                           ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _S,
+                           ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _S,
                            _P, _P, _S, _P, _P]),
     "vrs_sort_pairs": (_I, [_P, _P, _P, _S, _I, _P, _S, _P]),
     "vrs_sort_pairs_workspace_size": (_S, [_S]),
     "vrs_tile_ranges": (_I, [_P, _P, _S, _U, _P, _P]),
     "vrs_sort": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
-                      ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _S,
+                      ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _S,
                       _P, _P, _P, _S, _P, _P]),
     "vrs_render_foveated": (_I, [_P, _I, _P, _P, ctypes.POINTER(vrs_camera),
                                  ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _U,
                                  ctypes.POINTER(ctypes.c_void_p), _P, _S, _P, _P]),
+    "vrs_blend": (_I, [_P, _I, _P, _P, ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I,
+                       ctypes.POINTER(vrs_params), _P, _U, ctypes.POINTER(ctypes.c_void_p), _P, _S, _P, _P]),
+    "vrs_blend_stats": (_I, [_P, _I, _P, _P, ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I,
+                             ctypes.POINTER(vrs_params), _P, _U, ctypes.POINTER(ctypes.c_void_p), _P, _S, _P,
+                             _P]),
+    "vrs_compose": (_I, [ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params),
+                         _P, ctypes.POINTER(ctypes.c_void_p), _P, _S, _P]),
     "vrs_status_string": (ctypes.c_char_p, [_I]),
     "vrs_version": (ctypes.c_char_p, []),
 }

@@ -11,14 +11,21 @@ int launch_status(hipError_t e) { return e == hipSuccess ? VRS_OK : VRS_ERR_HIP;
 
 // Launchers defined in the kernel translation units.
 int launch_preprocess(const GaussPtrs&, const GeoViews&, const Knobs&, float*, uint32_t*, hipStream_t);
-int launch_duplicate(const GaussPtrs&, const GeoViews&, const Knobs&, const uint32_t*, uint64_t*, uint32_t*,
-                     size_t, uint32_t*, void*, int*, hipStream_t);
-size_t scan_ws_bytes(size_t n);
+int launch_duplicate(const GaussPtrs&, const GeoViews&, const Knobs&, const float*, const uint32_t*, uint64_t*,
+                     uint32_t*, size_t, uint32_t*, void*, int*, hipStream_t);
 size_t sort_ws_bytes(size_t capacity);
 int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, hipStream_t);
+int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*, bool, size_t, int, void*,
+                         hipStream_t);
+
+// Bytes per Gaussian and view in `proj`: the FP32 render record plus the FP64
+// tile-test record (TileGeo, 224 bytes) that instantiation reads.
+constexpr size_t kProjBytesPerSlot = kRec * sizeof(float) + 224;
+size_t dup_ws_bytes(size_t nslots) { return (nslots + scan_tmp_words(nslots) + 64) * sizeof(uint32_t); }
 int launch_tile_ranges(const uint64_t*, const uint32_t*, size_t, uint32_t, uint32_t*, hipStream_t);
-int launch_render(const float*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, uint32_t,
-                  const RenderViews&, const Knobs&, int, const uint8_t*, hipStream_t);
+int launch_blend(const float*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, uint32_t,
+                 const RenderViews&, const Knobs&, int, unsigned long long*, hipStream_t);
+int launch_compose(const RenderViews&, const uint8_t*, hipStream_t);
 bool window_supported(int w);
 
 int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, void* plan, size_t items_max, hipStream_t s);
@@ -141,14 +148,16 @@ Knobs knobs(const vrs_params* p) {
     return k;
 }
 
-GeoViews geo_views(const vrs_camera* cams, const Layout& L) {
+GeoViews geo_views(const vrs_camera* cams, const Layout& L, const vrs_params* p) {
     GeoViews G;
     memset(&G, 0, sizeof(G));
     G.n = L.n_views;
+    G.ln_amin = log(double(p->alpha_min));
     for (int v = 0; v < L.n_views; ++v) {
         GeoView& o = G.v[v];
         const ViewLayout& V = L.v[v];
         o.f = V.f;
+        o.inv_f = 1.0 / V.f;
         for (int k = 0; k < 3; ++k) {
             for (int j = 0; j < 3; ++j) o.R[3 * k + j] = cams[v].world_to_cam[4 * k + j];
             o.t[k] = cams[v].world_to_cam[4 * k + 3];
@@ -197,12 +206,12 @@ int vrs_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* fovea
     const int rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
     const size_t nv = size_t(n_views) * size_t(n);
-    out->proj_bytes = nv * kRec * sizeof(float);
+    out->proj_bytes = nv * kProjBytesPerSlot;
     out->counts_bytes = nv * sizeof(uint32_t);
     out->tiles_total = L.tiles_total;
     out->items_max = L.items_max;
     out->plan_bytes = L.plan_bytes;
-    const size_t a = scan_ws_bytes(nv), b = sort_ws_bytes(capacity);
+    const size_t a = dup_ws_bytes(nv), b = sort_ws_bytes(capacity);
     out->sort_ws_bytes = a > b ? a : b;
     out->render_ws_bytes = L.render_ws_floats * sizeof(float);
     return VRS_OK;
@@ -273,24 +282,27 @@ int vrs_preprocess(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fov
     rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
     if (g->n > 0 && (!proj || !counts || !aligned(proj, 16))) return VRS_ERR_INVALID_ARG;
-    return launch_preprocess(gauss_ptrs(g), geo_views(cams, L), knobs(p), static_cast<float*>(proj), counts,
+    return launch_preprocess(gauss_ptrs(g), geo_views(cams, L, p), knobs(p), static_cast<float*>(proj), counts,
                              reinterpret_cast<hipStream_t>(stream));
 }
 
 int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
-                  const vrs_params* p, const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
-                  uint32_t* n_inst_dev, void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream) {
+                  const vrs_params* p, const void* proj, const uint32_t* counts, uint64_t* keys, uint32_t* gids,
+                  size_t capacity, uint32_t* n_inst_dev, void* ws, size_t ws_bytes, int32_t* status_dev,
+                  vrs_stream_t stream) {
     int rc = check_gaussians(g);
     if (rc != VRS_OK) return rc;
     Layout L;
     rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
     const size_t nv = size_t(n_views) * size_t(g->n);
-    if (!n_inst_dev || (nv > 0 && (!counts || !ws)) || (capacity > 0 && (!keys || !gids))) return VRS_ERR_INVALID_ARG;
+    if (!n_inst_dev || (nv > 0 && (!counts || !ws || !proj)) || (capacity > 0 && (!keys || !gids)))
+        return VRS_ERR_INVALID_ARG;
     if (capacity > 0xFFFFFFFFull || nv > 0xFFFFFFFFull) return VRS_ERR_UNSUPPORTED;
-    if (ws_bytes < scan_ws_bytes(nv) || !aligned(keys, 8) || !aligned(ws, 16)) return VRS_ERR_INVALID_ARG;
-    return launch_duplicate(gauss_ptrs(g), geo_views(cams, L), knobs(p), counts, keys, gids, capacity, n_inst_dev,
-                            ws, status_dev, reinterpret_cast<hipStream_t>(stream));
+    if (ws_bytes < dup_ws_bytes(nv) || !aligned(keys, 8) || !aligned(ws, 16) || !aligned(proj, 16))
+        return VRS_ERR_INVALID_ARG;
+    return launch_duplicate(gauss_ptrs(g), geo_views(cams, L, p), knobs(p), static_cast<const float*>(proj), counts,
+                            keys, gids, capacity, n_inst_dev, ws, status_dev, reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t vrs_sort_pairs_workspace_size(size_t capacity) { return sort_ws_bytes(capacity); }
@@ -312,36 +324,41 @@ int vrs_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity
 }
 
 int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
-             const vrs_params* p, const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
-             uint32_t* n_inst_dev, uint32_t* ranges, void* ws, size_t ws_bytes, int32_t* status_dev,
-             vrs_stream_t stream) {
+             const vrs_params* p, const void* proj, const uint32_t* counts, uint64_t* keys, uint32_t* gids,
+             size_t capacity, uint32_t* n_inst_dev, uint32_t* ranges, void* ws, size_t ws_bytes,
+             int32_t* status_dev, vrs_stream_t stream) {
     Layout L;
     int rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
-    rc = vrs_duplicate(g, cams, foveas, n_views, p, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
+    if (!ranges && L.tiles_total > 0) return VRS_ERR_INVALID_ARG;
+    if (capacity > 0 && ws_bytes < sort_ws_bytes(capacity)) return VRS_ERR_INVALID_ARG;
+    rc = vrs_duplicate(g, cams, foveas, n_views, p, proj, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
                        status_dev, stream);
     if (rc != VRS_OK) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (capacity > 0) {
-        rc = vrs_sort_pairs(keys, gids, n_inst_dev, capacity, key_bits_for(L.tiles_total), ws, ws_bytes, stream);
+        // The first pass drops the dead keys of culled candidates.
+        rc = launch_sort_pairs_ex(keys, gids, n_inst_dev, n_inst_dev + 1, true, capacity,
+                                  key_bits_for(L.tiles_total), ws, s);
         if (rc != VRS_OK) return rc;
     }
-    return vrs_tile_ranges(keys, n_inst_dev, capacity, L.tiles_total, ranges, stream);
+    return launch_tile_ranges(keys, n_inst_dev + 1, capacity, L.tiles_total, ranges, s);
 }
 
-int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
-                        const vrs_camera* cams,
-                        const vrs_fovea* foveas, int32_t n_views, const vrs_params* p, const void* plan,
-                        uint32_t n_items, float* const* rgba, void* ws, size_t ws_bytes, int32_t* status_dev,
-                        vrs_stream_t stream) {
-    (void)status_dev;
-    Layout L;
+}  // extern "C"
+
+namespace {
+
+// Shared argument checks and tables of the render entry points.
+int render_setup(int32_t n, const void* proj, const uint32_t* gids, const uint32_t* ranges, const vrs_camera* cams,
+                 const vrs_fovea* foveas, int32_t n_views, const vrs_params* p, const void* plan, uint32_t n_items,
+                 float* const* rgba, void* ws, size_t ws_bytes, RenderViews& R, Layout& L) {
     int rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
-    if (n < 0 || !plan || !rgba || !ranges || n_items > L.items_max) return VRS_ERR_INVALID_ARG;
-    if (n_items > 0 && (!proj || !gids || !aligned(proj, 16))) return VRS_ERR_INVALID_ARG;
+    if (n < 0 || !plan || !rgba || n_items > L.items_max) return VRS_ERR_INVALID_ARG;
+    if (n_items > 0 && (!proj || !gids || !ranges || !aligned(proj, 16))) return VRS_ERR_INVALID_ARG;
     if (L.render_ws_floats > 0 && (!ws || ws_bytes < L.render_ws_floats * sizeof(float)))
         return VRS_ERR_INVALID_ARG;
-    RenderViews R;
     memset(&R, 0, sizeof(R));
     R.n = n_views;
     for (int v = 0; v < n_views; ++v) {
@@ -372,10 +389,63 @@ int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const
         o.cls_off = V.cls_off;
         o.foveated = V.foveated;
     }
-    const uint8_t* cls = static_cast<const uint8_t*>(plan) + kPlanItemsOff + size_t(L.items_max) * 4;
-    const uint32_t* items = reinterpret_cast<const uint32_t*>(static_cast<const char*>(plan) + kPlanItemsOff);
-    return launch_render(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items, R, knobs(p),
-                         p->window, cls, reinterpret_cast<hipStream_t>(stream));
+    return VRS_OK;
+}
+
+const uint32_t* plan_items(const void* plan) {
+    return reinterpret_cast<const uint32_t*>(static_cast<const char*>(plan) + kPlanItemsOff);
+}
+const uint8_t* plan_classes(const void* plan, const Layout& L) {
+    return static_cast<const uint8_t*>(plan) + kPlanItemsOff + size_t(L.items_max) * 4;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vrs_blend(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges, const vrs_camera* cams,
+              const vrs_fovea* foveas, int32_t n_views, const vrs_params* p, const void* plan, uint32_t n_items,
+              float* const* rgba, void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream) {
+    (void)status_dev;
+    RenderViews R;
+    Layout L;
+    int rc = render_setup(n, proj, gids, ranges, cams, foveas, n_views, p, plan, n_items, rgba, ws, ws_bytes, R, L);
+    if (rc != VRS_OK) return rc;
+    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, plan_items(plan), n_items, R,
+                        knobs(p), p->window, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
+                    const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,
+                    const void* plan, uint32_t n_items, float* const* rgba, void* ws, size_t ws_bytes,
+                    uint64_t* counters_dev, vrs_stream_t stream) {
+    RenderViews R;
+    Layout L;
+    if (!counters_dev) return VRS_ERR_INVALID_ARG;
+    int rc = render_setup(n, proj, gids, ranges, cams, foveas, n_views, p, plan, n_items, rgba, ws, ws_bytes, R, L);
+    if (rc != VRS_OK) return rc;
+    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, plan_items(plan), n_items, R,
+                        knobs(p), p->window, reinterpret_cast<unsigned long long*>(counters_dev),
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
+int vrs_compose(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,
+                const void* plan, float* const* rgba, void* ws, size_t ws_bytes, vrs_stream_t stream) {
+    RenderViews R;
+    Layout L;
+    int rc = render_setup(0, nullptr, nullptr, nullptr, cams, foveas, n_views, p, plan, 0, rgba, ws, ws_bytes, R, L);
+    if (rc != VRS_OK) return rc;
+    return launch_compose(R, plan_classes(plan, L), reinterpret_cast<hipStream_t>(stream));
+}
+
+int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
+                        const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,
+                        const void* plan, uint32_t n_items, float* const* rgba, void* ws, size_t ws_bytes,
+                        int32_t* status_dev, vrs_stream_t stream) {
+    int rc = vrs_blend(proj, n, gids, ranges, cams, foveas, n_views, p, plan, n_items, rgba, ws, ws_bytes,
+                       status_dev, stream);
+    if (rc != VRS_OK) return rc;
+    return vrs_compose(cams, foveas, n_views, p, plan, rgba, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -111,12 +111,16 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int W>
+// STATS = true is the instrumented variant: it also counts, per launch,
+// evaluated (sample, entry) pairs, pairs that reach alpha_min, in-image
+// samples, samples stopped by t_min and list entries staged.
+template <int W, bool STATS>
 __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restrict__ proj, uint32_t n_gauss,
                                                            const uint32_t* __restrict__ gids,
                                                            const uint32_t* __restrict__ ranges,
                                                            const uint32_t* __restrict__ items,
-                                                           RenderViews views, Knobs kn) {
+                                                           RenderViews views, Knobs kn,
+                                                           unsigned long long* __restrict__ stats) {
     __shared__ float4 stage[kRenderThreads / 64][kBatch][kStage];
     const uint32_t item = items[blockIdx.x];
     const int v = item_view(item);
@@ -160,10 +164,12 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
     float4(*st)[kStage] = stage[wv];
     const float amax = kn.alpha_max, tmin = kn.t_min;
+    uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0;
 
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBatch) {
         if (__ballot(acc.alive) == 0ull) break;
         const int nb = int(min(uint32_t(kBatch), rg.y - b0));
+        if (STATS) n_staged += lane < nb ? 1u : 0u;
         if (lane < nb) {
             const uint32_t gid = gids[b0 + lane];
             const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
@@ -191,6 +197,10 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
             const float q = fmaf(z1, z1, z2 * z2);
             const float h2 = h * h;
             const bool pass = acc.alive && (h > 0.f) && (q <= f2.y * h2);
+            if (STATS) {
+                n_pairs += acc.alive ? 1u : 0u;
+                n_contrib += pass ? 1u : 0u;
+            }
             if (__ballot(pass) != 0ull) {  // wave-uniform
                 const float4 f3 = st[j][3], f4 = st[j][4], f5 = st[j][5], f6 = st[j][6];
                 Slot x;
@@ -213,6 +223,13 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
 #pragma unroll
     for (int i = 0; i < W; ++i) acc.blend(win.a[i], win.r[i], win.g[i], win.b[i], tmin);
 
+    if (STATS) {
+        atomicAdd(&stats[0], (unsigned long long)n_pairs);
+        atomicAdd(&stats[1], (unsigned long long)n_contrib);
+        atomicAdd(&stats[2], (unsigned long long)(inimg ? 1u : 0u));
+        atomicAdd(&stats[3], (unsigned long long)((inimg && !acc.alive) ? 1u : 0u));
+        atomicAdd(&stats[4], (unsigned long long)n_staged);
+    }
     float o[4] = {acc.cr + acc.T * kn.bg[0], acc.cg + acc.T * kn.bg[1], acc.cb + acc.T * kn.bg[2], 1.f - acc.T};
     float* dst = V.foveated ? V.pre : V.out;
     const size_t plane = size_t(V.W) * size_t(V.H);
@@ -288,9 +305,13 @@ __global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __
 template <int W>
 static void launch_render_w(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
                             const uint32_t* items, uint32_t n_items, const RenderViews& views, const Knobs& kn,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_render<W>, dim3(n_items), dim3(kRenderThreads), 0, s, proj, n_gauss, gids, ranges, items,
-                       views, kn);
+                            unsigned long long* stats, hipStream_t s) {
+    if (stats)
+        hipLaunchKernelGGL((k_render<W, true>), dim3(n_items), dim3(kRenderThreads), 0, s, proj, n_gauss, gids,
+                           ranges, items, views, kn, stats);
+    else
+        hipLaunchKernelGGL((k_render<W, false>), dim3(n_items), dim3(kRenderThreads), 0, s, proj, n_gauss, gids,
+                           ranges, items, views, kn, stats);
 }
 
 bool window_supported(int w) {
@@ -300,26 +321,21 @@ bool window_supported(int w) {
     }
 }
 
-int launch_render(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
-                  const uint32_t* items, uint32_t n_items, const RenderViews& views, const Knobs& kn, int window,
-                  const uint8_t* cls, hipStream_t s) {
-    if (n_items > 0) {
-        switch (window) {
-            case 1: launch_render_w<1>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 2: launch_render_w<2>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 3: launch_render_w<3>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 4: launch_render_w<4>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 6: launch_render_w<6>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 8: launch_render_w<8>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 12: launch_render_w<12>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 16: launch_render_w<16>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 24: launch_render_w<24>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            case 32: launch_render_w<32>(proj, n_gauss, gids, ranges, items, n_items, views, kn, s); break;
-            default: return VRS_ERR_UNSUPPORTED;
-        }
-        const int rc = launch_status(hipGetLastError());
-        if (rc != VRS_OK) return rc;
+int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
+                 const uint32_t* items, uint32_t n_items, const RenderViews& views, const Knobs& kn, int window,
+                 unsigned long long* stats, hipStream_t s) {
+    if (n_items == 0) return VRS_OK;
+#define VRS_W(w) \
+    case w: launch_render_w<w>(proj, n_gauss, gids, ranges, items, n_items, views, kn, stats, s); break;
+    switch (window) {
+        VRS_W(1) VRS_W(2) VRS_W(3) VRS_W(4) VRS_W(6) VRS_W(8) VRS_W(12) VRS_W(16) VRS_W(24) VRS_W(32)
+        default: return VRS_ERR_UNSUPPORTED;
     }
+#undef VRS_W
+    return launch_status(hipGetLastError());
+}
+
+int launch_compose(const RenderViews& views, const uint8_t* cls, hipStream_t s) {
     for (int v = 0; v < views.n; ++v) {
         const RenderView& V = views.v[v];
         if (!V.foveated) continue;

@@ -1,15 +1,20 @@
 // K4: stable LSD radix sort of (uint64 key, uint32 value) pairs with 8-bit
-// digits, and K5: per-tile [start, end) ranges of the sorted keys.
+// digits, K5: per-tile [start, end) ranges of the sorted keys, and the
+// exclusive scan shared with the instantiation stage.
 //
 // Each pass is reduce-then-scan: (1) every block counts the digits of its
-// 4096-key tile in LDS, (2) one block scans the digit-major [256][blocks]
-// histogram, (3) every block ranks its keys stably -- each wave owns a
-// contiguous 1024-key slice, ranks within a 64-key step by matching digits
-// with ballots, and the per-wave digit counts are prefix-summed across waves
-// -- and scatters to its global offsets.  No inter-block waiting, so the
-// passes are deterministic and need no forward-progress assumptions.  The
-// number of pairs is read on the device, so the grid covers `capacity` and
-// surplus blocks only contribute zero counts.
+// 4096-key tile in LDS, (2) a three-phase multi-block scan of the digit-major
+// [256][blocks] histogram gives every (digit, block) its output offset, (3)
+// every block ranks its keys stably -- each wave owns a contiguous 1024-key
+// slice, ranks within a 64-key step by matching digits with ballots, and the
+// per-wave digit counts are prefix-summed across waves -- and scatters them.
+// No inter-block waiting, so passes are deterministic and need no
+// forward-progress assumptions.  Pair counts are read on the device, so the
+// grid covers `capacity` and surplus blocks only contribute zero counts.
+//
+// The first pass can drop dead keys (all ones): instantiation writes one for
+// every candidate tile that fails the tile test, and they never reach the
+// later passes.
 #include "vrs_internal.h"
 
 namespace vrs {
@@ -19,7 +24,109 @@ constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortItemsPerLane = 16;
 constexpr int kSortTile = kSortThreads * kSortItemsPerLane;  // 4096
 constexpr int kRadix = 256;
+constexpr uint64_t kDeadKey = ~0ull;
 
+// ---------------------------------------------------------------------------
+// Exclusive scan of uint32 (per-block scan, scan of block sums, add-back).
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* sh, uint32_t& total) {
+    const int t = threadIdx.x;
+    sh[t] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const uint32_t y = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += y;
+        __syncthreads();
+    }
+    total = sh[kScanThreads - 1];
+    const uint32_t incl = sh[t];
+    __syncthreads();
+    return incl - x;
+}
+
+// in and out may alias: every thread reads its items before writing them.
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const uint32_t* in, uint32_t* out,
+                                                             uint32_t* __restrict__ sums, size_t n) {
+    __shared__ uint32_t sh[kScanThreads];
+    const size_t base = size_t(blockIdx.x) * kScanTile + size_t(threadIdx.x) * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(s, sh, tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Single block: exclusive scan of the block sums in chunks with a carry.
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t* __restrict__ sums, size_t nb,
+                                                            uint32_t* __restrict__ total) {
+    __shared__ uint32_t sh[kScanThreads];
+    uint32_t carry = 0;
+    for (size_t c0 = 0; c0 < nb; c0 += kScanTile) {
+        const size_t base = c0 + size_t(threadIdx.x) * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < nb ? sums[base + k] : 0u;
+            s += v[k];
+        }
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(s, sh, tot) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < nb) sums[base + k] = ex;
+            ex += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_add(uint32_t* __restrict__ out,
+                                                           const uint32_t* __restrict__ sums, size_t n) {
+    const uint32_t add = sums[blockIdx.x];
+    const size_t base = size_t(blockIdx.x) * kScanTile;
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+        if (base + k < n) out[base + k] += add;
+}
+
+__global__ void k_store_zero(uint32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+size_t scan_tmp_words(size_t n) { return (n + kScanTile - 1) / kScanTile + 64; }
+
+int launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* total, uint32_t* tmp,
+                          hipStream_t s) {
+    if (n == 0) {
+        if (total) hipLaunchKernelGGL(k_store_zero, dim3(1), dim3(64), 0, s, total);
+        return launch_status(hipGetLastError());
+    }
+    const size_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanThreads), 0, s, in, out, tmp, n);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, total);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, s, out, tmp, n);
+    return launch_status(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort.
+// ---------------------------------------------------------------------------
 __device__ inline size_t n_eff(const uint32_t* n_dev, size_t capacity) {
     const size_t n = size_t(*n_dev);
     return n < capacity ? n : capacity;
@@ -27,7 +134,7 @@ __device__ inline size_t n_eff(const uint32_t* n_dev, size_t capacity) {
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ n_dev,
-                                                             size_t capacity, int shift,
+                                                             size_t capacity, int shift, int drop,
                                                              uint32_t* __restrict__ hist, int nblocks) {
     __shared__ uint32_t cnt[kRadix];
     cnt[threadIdx.x] = 0;
@@ -36,46 +143,13 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __r
     const size_t base = size_t(blockIdx.x) * kSortTile;
     for (int k = 0; k < kSortItemsPerLane; ++k) {
         const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&cnt[uint32_t(keys[idx] >> shift) & 0xFFu], 1u);
+        if (idx < n) {
+            const uint64_t key = keys[idx];
+            if (!(drop && key == kDeadKey)) atomicAdd(&cnt[uint32_t(key >> shift) & 0xFFu], 1u);
+        }
     }
     __syncthreads();
     hist[size_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
-}
-
-// Single block exclusive scan of `len` words in chunks with a carry.
-constexpr int kHistScanThreads = 1024;
-__global__ void __launch_bounds__(kHistScanThreads) k_hist_scan(uint32_t* __restrict__ h, size_t len) {
-    __shared__ uint32_t sh[kHistScanThreads];
-    constexpr int kItems = 8;
-    uint32_t carry = 0;
-    const int t = threadIdx.x;
-    for (size_t c0 = 0; c0 < len; c0 += size_t(kHistScanThreads) * kItems) {
-        const size_t b = c0 + size_t(t) * kItems;
-        uint32_t v[kItems];
-        uint32_t s = 0;
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            v[k] = b + k < len ? h[b + k] : 0u;
-            s += v[k];
-        }
-        sh[t] = s;
-        __syncthreads();
-        for (int off = 1; off < kHistScanThreads; off <<= 1) {
-            const uint32_t y = t >= off ? sh[t - off] : 0u;
-            __syncthreads();
-            sh[t] += y;
-            __syncthreads();
-        }
-        uint32_t ex = sh[t] - s + carry;
-        const uint32_t tot = sh[kHistScanThreads - 1];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            if (b + k < len) h[b + k] = ex;
-            ex += v[k];
-        }
-        carry += tot;
-    }
 }
 
 __device__ inline uint64_t lanemask_lt() {
@@ -85,7 +159,7 @@ __device__ inline uint64_t lanemask_lt() {
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, size_t capacity, int shift,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, size_t capacity, int shift, int drop,
     const uint32_t* __restrict__ hist, int nblocks) {
     __shared__ uint32_t wcnt[kSortWaves][kRadix];
     __shared__ uint32_t goff[kRadix];
@@ -96,19 +170,22 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     goff[t] = hist[size_t(t) * nblocks + blockIdx.x];
     __syncthreads();
     const size_t n = n_eff(n_dev, capacity);
-    const size_t base = size_t(blockIdx.x) * kSortTile + size_t(w) * (kSortTile / kSortWaves);
     if (size_t(blockIdx.x) * kSortTile >= n) return;  // whole block empty (uniform)
+    const size_t base = size_t(blockIdx.x) * kSortTile + size_t(w) * (kSortTile / kSortWaves);
 
     uint64_t key[kSortItemsPerLane];
     uint32_t val[kSortItemsPerLane];
     uint32_t rank[kSortItemsPerLane];
+    bool live[kSortItemsPerLane];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int it = 0; it < kSortItemsPerLane; ++it) {
         const size_t idx = base + size_t(it) * 64 + lane;
-        const bool ok = idx < n;
-        key[it] = ok ? kin[idx] : 0ull;
-        val[it] = ok ? vin[idx] : 0u;
+        const bool in = idx < n;
+        key[it] = in ? kin[idx] : 0ull;
+        val[it] = in ? vin[idx] : 0u;
+        const bool ok = in && !(drop && key[it] == kDeadKey);
+        live[it] = ok;
         const uint32_t d = uint32_t(key[it] >> shift) & 0xFFu;
         // Lanes holding the same digit: intersect the ballots of each bit.
         uint64_t m = __ballot(ok);
@@ -140,8 +217,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kSortItemsPerLane; ++it) {
-        const size_t idx = base + size_t(it) * 64 + lane;
-        if (idx < n) {
+        if (live[it]) {
             const uint32_t d = uint32_t(key[it] >> shift) & 0xFFu;
             const size_t pos = size_t(goff[d]) + wcnt[w][d] + rank[it];
             kout[pos] = key[it];
@@ -177,11 +253,14 @@ __global__ void k_tile_ranges(const uint64_t* __restrict__ keys, const uint32_t*
 }
 
 // ---------------------------------------------------------------------------
+static size_t sort_blocks(size_t capacity) { return (capacity + kSortTile - 1) / kSortTile; }
+
 size_t sort_ws_bytes(size_t capacity) {
-    const size_t nb = (capacity + kSortTile - 1) / kSortTile;
+    const size_t nb = sort_blocks(capacity) ? sort_blocks(capacity) : 1;
     size_t b = capacity * (sizeof(uint64_t) + sizeof(uint32_t));  // ping-pong buffers
     b = (b + 255) & ~size_t(255);
-    b += (size_t(kRadix) * (nb ? nb : 1) + 64) * sizeof(uint32_t);   // histogram
+    const size_t hist = size_t(kRadix) * nb;
+    b += (hist + scan_tmp_words(hist) + 64) * sizeof(uint32_t);
     return b;
 }
 
@@ -192,33 +271,46 @@ int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     return launch_status(hipGetLastError());
 }
 
-int launch_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity,
-                      int key_bits, void* ws, hipStream_t s) {
+// Sort min(*n_first, capacity) pairs; with drop_first the first pass drops
+// dead keys and the remaining passes sort min(*n_rest, capacity) pairs.
+int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first, const uint32_t* n_rest,
+                         bool drop_first, size_t capacity, int key_bits, void* ws, hipStream_t s) {
     if (capacity == 0 || key_bits <= 0) return VRS_OK;
-    const int nb = int((capacity + kSortTile - 1) / kSortTile);
+    const int nb = int(sort_blocks(capacity));
     uint64_t* k2 = static_cast<uint64_t*>(ws);
     uint32_t* v2 = reinterpret_cast<uint32_t*>(k2 + capacity);
     size_t off = capacity * (sizeof(uint64_t) + sizeof(uint32_t));
     off = (off + 255) & ~size_t(255);
     uint32_t* hist = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + off);
+    const size_t hist_len = size_t(kRadix) * nb;
+    uint32_t* tmp = hist + hist_len;
     const int passes = (key_bits + 7) / 8;
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n_dev, capacity, shift, hist, nb);
-        hipLaunchKernelGGL(k_hist_scan, dim3(1), dim3(kHistScanThreads), 0, s, hist, size_t(kRadix) * nb);
+        const int drop = (p == 0 && drop_first) ? 1 : 0;
+        const uint32_t* n_dev = (p == 0 || !drop_first) ? n_first : n_rest;
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n_dev, capacity, shift, drop, hist,
+                           nb);
+        int rc = launch_exclusive_scan(hist, hist, hist_len, nullptr, tmp, s);
+        if (rc != VRS_OK) return rc;
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, va, kb, vb, n_dev, capacity,
-                           shift, hist, nb);
+                           shift, drop, hist, nb);
         uint64_t* tk = ka; ka = kb; kb = tk;
         uint32_t* tv = va; va = vb; vb = tv;
     }
     if (ka != keys) {
         const size_t blocks = (capacity + 255) / 256;
         hipLaunchKernelGGL(k_copy_pairs, dim3(blocks < 4096 ? blocks : 4096), dim3(256), 0, s, ka, va, keys, vals,
-                           n_dev, capacity);
+                           drop_first ? n_rest : n_first, capacity);
     }
     return launch_status(hipGetLastError());
+}
+
+int launch_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity, int key_bits,
+                      void* ws, hipStream_t s) {
+    return launch_sort_pairs_ex(keys, vals, n_dev, n_dev, false, capacity, key_bits, ws, s);
 }
 
 int launch_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity, uint32_t tiles_total,

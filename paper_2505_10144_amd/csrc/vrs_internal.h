@@ -46,6 +46,7 @@ struct GaussPtrs {
 // Geometry of one view for the per-Gaussian kernels.
 struct GeoView {
     double f;
+    double inv_f;
     float R[9];
     float t[3];
     float cx, cy;
@@ -57,6 +58,7 @@ struct GeoView {
 
 struct GeoViews {
     int n;
+    double ln_amin;  // ln(alpha_min)
     GeoView v[VRS_MAX_VIEWS];
 };
 
@@ -133,5 +135,10 @@ constexpr size_t kPlanItemsOff = 256;
 
 // Launch helpers (host).
 int launch_status(hipError_t e);
+size_t scan_tmp_words(size_t n);
+// Exclusive scan of n uint32 (in may equal out); *total (if non-null) gets
+// the sum; tmp holds scan_tmp_words(n) words.
+int launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* total, uint32_t* tmp,
+                          hipStream_t s);
 
 }  // namespace vrs

@@ -90,7 +90,7 @@ class Renderer:
         self.proj = u8(sizes.proj_bytes)
         self.counts = torch.empty(max(self.V * self.n, 1), dtype=torch.int32, device=dev)
         self.ranges = torch.empty(max(2 * self.tiles_total, 2), dtype=torch.int32, device=dev)
-        self.n_inst = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.n_inst = torch.zeros(2, dtype=torch.int32, device=dev)  # [candidates, kept]
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.plan = u8(sizes.plan_bytes)
         self.render_ws = u8(sizes.render_ws_bytes)
@@ -131,10 +131,10 @@ class Renderer:
         self.preprocess(g)
         self.status.zero_()
         L.call("vrs_duplicate", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
-               ctypes.byref(self.c_params), _ptr(self.counts), _ptr(self.keys), _ptr(self.gids),
-               ctypes.c_size_t(0), _ptr(self.n_inst), _ptr(self.sort_ws),
+               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
+               _ptr(self.gids), ctypes.c_size_t(0), _ptr(self.n_inst), _ptr(self.sort_ws),
                ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status), _stream(self.stream))
-        need = int(self.n_inst.item())
+        need = int(self.n_inst[0].item())
         if need > self.capacity:
             self._alloc_instances(max(int(need * headroom), 1024))
         self.status.zero_()
@@ -148,8 +148,8 @@ class Renderer:
 
     def duplicate(self, g: Gaussians):
         L.call("vrs_duplicate", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
-               ctypes.byref(self.c_params), _ptr(self.counts), _ptr(self.keys), _ptr(self.gids),
-               ctypes.c_size_t(self.capacity), _ptr(self.n_inst), _ptr(self.sort_ws),
+               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
+               _ptr(self.gids), ctypes.c_size_t(self.capacity), _ptr(self.n_inst), _ptr(self.sort_ws),
                ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status), _stream(self.stream))
 
     def key_bits(self):
@@ -160,10 +160,32 @@ class Renderer:
 
     def sort(self, g: Gaussians):
         L.call("vrs_sort", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
-               ctypes.byref(self.c_params), _ptr(self.counts), _ptr(self.keys), _ptr(self.gids),
+               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
+               _ptr(self.gids),
                ctypes.c_size_t(self.capacity), _ptr(self.n_inst), _ptr(self.ranges),
                _ptr(self.sort_ws), ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status),
                _stream(self.stream))
+
+    def blend_only(self):
+        L.call("vrs_blend", _ptr(self.proj), self.n, _ptr(self.gids), _ptr(self.ranges),
+               self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), _ptr(self.plan),
+               ctypes.c_uint32(self.n_items), self._img_ptrs, _ptr(self.render_ws),
+               ctypes.c_size_t(self.render_ws.numel()), _ptr(self.status), _stream(self.stream))
+
+    def compose(self):
+        L.call("vrs_compose", self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), _ptr(self.plan),
+               self._img_ptrs, _ptr(self.render_ws), ctypes.c_size_t(self.render_ws.numel()),
+               _stream(self.stream))
+
+    def blend_stats(self):
+        """Instrumented blend: returns dict of work counters (one sync)."""
+        c = torch.zeros(5, dtype=torch.int64, device=self.device)
+        L.call("vrs_blend_stats", _ptr(self.proj), self.n, _ptr(self.gids), _ptr(self.ranges),
+               self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), _ptr(self.plan),
+               ctypes.c_uint32(self.n_items), self._img_ptrs, _ptr(self.render_ws),
+               ctypes.c_size_t(self.render_ws.numel()), _ptr(c), _stream(self.stream))
+        v = c.cpu().tolist()
+        return dict(pairs=v[0], contrib=v[1], samples=v[2], stopped=v[3], staged=v[4])
 
     def blend(self):
         L.call("vrs_render_foveated", _ptr(self.proj), self.n, _ptr(self.gids), _ptr(self.ranges),
@@ -187,7 +209,7 @@ class Renderer:
         st = int(self.status.item())
         if st != L.VRS_OK:
             raise L.VrsError("device", st)
-        return int(self.n_inst.item())
+        return int(self.n_inst[1].item())
 
     # -- views of the plan, for tests and tools -----------------------------------
     def plan_items(self) -> np.ndarray:

@@ -206,12 +206,15 @@ def _stage_setup(R, scene, cams, fovs, params):
 def test_instances_and_keys_match_oracle(R):
     scene, cams, fovs, params = synth.config_stereo(3, n=8000, width=256, height=224)
     r, g = _stage_setup(R, scene, cams, fovs, params)
-    n = int(r.n_inst.item())
-    keys = r.keys[:n].cpu().numpy().view(np.uint64)
-    gids = r.gids[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    n_cand, n_kept = (int(x) for x in r.n_inst.cpu().tolist())
+    keys = r.keys[:n_cand].cpu().numpy().view(np.uint64)
+    gids = r.gids[:n_cand].cpu().numpy().view(np.uint32).astype(np.int64)
+    live = keys != np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert int(live.sum()) == n_kept
+    keys, gids = keys[live], gids[live]
     ref = oracle.render(scene, cams, fovs, params, OracleOptions(shade=False))
     assert int(ref["inst_border"].sum()) == 0
-    assert len(ref["gids"]) == n
+    assert len(ref["gids"]) == n_kept
     s32 = np.uint64(32)
     gpu = {(int(k >> s32), int(gg)): int(k & np.uint64(0xFFFFFFFF)) for k, gg in zip(keys, gids)}
     ora = {(int(k >> s32), int(gg)): int(k & np.uint64(0xFFFFFFFF)) for k, gg in zip(ref["keys"], ref["gids"])}
@@ -221,16 +224,19 @@ def test_instances_and_keys_match_oracle(R):
     assert diffs.max() <= 1
     assert (diffs > 0).mean() < 1e-3
     # Instances are written in (view, Gaussian, tile) order.
-    order = np.lexsort((keys >> s32, gids))
     view = (keys >> s32).astype(np.int64) >= ref["view_offsets"][1]
     assert np.all(np.diff(view.astype(np.int64)) >= 0)
-    # Per-(view, Gaussian) counts equal the oracle's.
+    for v in (False, True):
+        gv = gids[view == v]
+        assert np.all(np.diff(gv) >= 0)
+    # Candidate counts bound the oracle's exact per-(view, Gaussian) counts.
     cnt = r.counts[: 2 * scene.n].cpu().numpy().reshape(2, scene.n)
     otile = (ref["keys"] >> s32).astype(np.int64)
     for v in range(2):
         inview = (otile >= ref["view_offsets"][v]) & (otile < ref["view_offsets"][v] + ref["grids"][v].n)
         oc = np.bincount(ref["gids"][inview].astype(np.int64), minlength=scene.n)
-        assert np.array_equal(cnt[v], oc)
+        assert np.all(cnt[v] >= oc)
+        assert np.array_equal(cnt[v] > 0, ref["pre"][v]["valid"] & (cnt[v] > 0))
 
 
 def test_sort_pairs_bit_exact_on_gpu_keys(R):
@@ -238,7 +244,7 @@ def test_sort_pairs_bit_exact_on_gpu_keys(R):
     import ctypes
     scene, cams, fovs, params = synth.config_stereo(4, n=20000, width=384, height=320)
     r, g = _stage_setup(R, scene, cams, fovs, params)
-    n = int(r.n_inst.item())
+    n = int(r.n_inst[0].item())
     k0 = r.keys[:n].cpu().numpy().view(np.uint64).copy()
     v0 = r.gids[:n].cpu().numpy().view(np.uint32).copy()
     L.call("vrs_sort_pairs", ctypes.c_void_p(r.keys.data_ptr()), ctypes.c_void_p(r.gids.data_ptr()),
@@ -248,15 +254,20 @@ def test_sort_pairs_bit_exact_on_gpu_keys(R):
     torch.cuda.synchronize()
     ks = r.keys[:n].cpu().numpy().view(np.uint64)
     vs = r.gids[:n].cpu().numpy().view(np.uint32)
-    order = np.lexsort((v0, k0))
+    order = np.argsort(k0, kind="stable")
     assert np.array_equal(ks, k0[order]) and np.array_equal(vs, v0[order])
+    # The kept instances come out in (key, gid) order.
+    n_kept = int(r.n_inst[1].item())
+    live = k0 != np.uint64(0xFFFFFFFFFFFFFFFF)
+    lo = np.lexsort((v0[live], k0[live]))
+    assert np.array_equal(ks[:n_kept], k0[live][lo]) and np.array_equal(vs[:n_kept], v0[live][lo])
     # Ranges from the sorted keys equal the oracle's scan of the same keys.
-    L.call("vrs_tile_ranges", ctypes.c_void_p(r.keys.data_ptr()), ctypes.c_void_p(r.n_inst.data_ptr()),
+    L.call("vrs_tile_ranges", ctypes.c_void_p(r.keys.data_ptr()), ctypes.c_void_p(r.n_inst.data_ptr() + 4),
            ctypes.c_size_t(r.capacity), ctypes.c_uint32(r.tiles_total), ctypes.c_void_p(r.ranges.data_ptr()),
            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     rg = r.ranges[: 2 * r.tiles_total].cpu().numpy().view(np.uint32).reshape(-1, 2)
-    assert np.array_equal(rg, otiles.tile_ranges(ks, r.tiles_total))
+    assert np.array_equal(rg, otiles.tile_ranges(ks[:n_kept], r.tiles_total))
 
 
 @pytest.mark.parametrize("n,bits,dups", [(0, 40, 1), (1, 40, 1), (4095, 64, 1), (4097, 33, 7),
@@ -299,14 +310,14 @@ def test_capacity_overflow_is_reported_and_recoverable(R):
     r.sort(g)
     torch.cuda.synchronize()
     assert int(r.status.item()) == L.VRS_ERR_CAPACITY
-    need = int(r.n_inst.item())
+    need = int(r.n_inst[0].item())
     assert need > 64 and r.keys.numel() == 64
     with pytest.raises(L.VrsError):
         r.check()
     r2 = R.Renderer(cams, fovs, params, scene.n, capacity=need)
     r2.render(g)
     torch.cuda.synchronize()
-    assert r2.check() == need
+    assert 0 < r2.check() <= need
 
 
 def test_record_colours_and_alpha(R):
