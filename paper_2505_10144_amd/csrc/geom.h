@@ -169,7 +169,8 @@ __device__ inline bool make_geo(const GaussLocal& G, const GeoView& V, const Kno
 // the x' range, likewise for y.  The whole grid when the cone comes within
 // 0.1 degree of the plane z = 0.  Only square roots: cos/sin of beta follow
 // from tan(beta).
-__device__ inline void cone_tiles(const Geo& g, const GeoView& V, int& tx0, int& tx1, int& ty0, int& ty1) {
+__device__ inline void cone_tiles(const Geo& g, const GeoView& V, int& tx0, int& tx1, int& ty0, int& ty1,
+                                  float bbox[4]) {
     const double rq = sqrt(fmax(g.tg.kappa, 0.0) * g.lam_max);
     const double hyp = sqrt(rq * rq + V.f * V.f);
     const double sb = rq / hyp, cb = V.f / hyp;
@@ -178,6 +179,7 @@ __device__ inline void cone_tiles(const Geo& g, const GeoView& V, int& tx0, int&
     // cos(theta_u + beta) <= cos(89.9 deg)
     if (uz * cb - st * sb <= 1.7453283658983088e-3) {
         tx0 = 0; ty0 = 0; tx1 = V.ntx - 1; ty1 = V.nty - 1;
+        bbox[0] = -INFINITY; bbox[1] = -INFINITY; bbox[2] = INFINITY; bbox[3] = INFINITY;
         return;
     }
     const double inv_a = 1.0 / (uz * uz - sb * sb);
@@ -188,6 +190,11 @@ __device__ inline void cone_tiles(const Geo& g, const GeoView& V, int& tx0, int&
     const double pxhi = double(V.cx) + V.f * (g.u[0] * uz + sb * dx) * inv_a + m;
     const double pylo = double(V.cy) + V.f * (g.u[1] * uz - sb * dy) * inv_a - m;
     const double pyhi = double(V.cy) + V.f * (g.u[1] * uz + sb * dy) * inv_a + m;
+    // Pixel box, rounded outwards to whole pixels.
+    bbox[0] = float(floor(pxlo));
+    bbox[1] = float(floor(pylo));
+    bbox[2] = float(ceil(pxhi));
+    bbox[3] = float(ceil(pyhi));
     if (pxhi < 0.0 || pylo > double(V.H) || pyhi < 0.0 || pxlo > double(V.W)) {
         tx0 = 1; tx1 = 0; ty0 = 1; ty1 = 0;  // empty
         return;

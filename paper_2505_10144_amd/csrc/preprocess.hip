@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
             continue;
         }
         int tx0, tx1, ty0, ty1;
-        cone_tiles(geo, V, tx0, tx1, ty0, ty1);
+        float bbox[4];
+        cone_tiles(geo, V, tx0, tx1, ty0, ty1, bbox);
         const int ncx = max(tx1 - tx0 + 1, 0), ncy = max(ty1 - ty0 + 1, 0);
         TileGeo& t = geo.tg;
         t.tx0 = tx0;
@@ -83,68 +84,142 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
         t.count = ncx * ncy;
         counts[slot] = uint32_t(ncx * ncy);
         tgeo[slot] = t;
-        // Colour from the eye centre o = -R^T t.
-        double eye[3];
-        for (int c = 0; c < 3; ++c)
-            eye[c] = -(double(V.R[c]) * V.t[0] + double(V.R[3 + c]) * V.t[1] + double(V.R[6 + c]) * V.t[2]);
-        const double dir[3] = {G.mu[0] - eye[0], G.mu[1] - eye[1], G.mu[2] - eye[2]};
-        const double idn = 1.0 / sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-        const float fd[3] = {float(dir[0] * idn), float(dir[1] * idn), float(dir[2] * idn)};
-        float rgb[3];
-        sh_eval(g, i, fd, rgb);
-        // Render record (field map in vrs_internal.h).
+        // Render record (field map in vrs_internal.h); the colour (fields
+        // 25..27) is written by k_color.
         const double xi = floor(t.x0), yi = floor(t.y0);
         const float zs = float(sqrt(0.5 / M_LN2));  // |z|^2 = (log2 e / 2) D^2
         float4* dst = reinterpret_cast<float4*>(proj + slot * kRec);
         dst[0] = make_float4(float(xi), float(yi), float(t.x0 - xi), float(t.y0 - yi));
         dst[1] = make_float4(float(t.M[0]) * zs, float(t.M[1]) * zs, float(t.M[2]) * zs, float(t.M[3]) * zs);
         dst[2] = make_float4(float(t.a3x), float(t.a3y), float(geo.l2s), float(t.kappa * (0.5 * M_LOG2E)));
-        dst[3] = make_float4(float(t.n0), float(t.nx), float(t.ny), 0.f);
+        dst[3] = make_float4(float(t.n0), float(t.nx), float(t.ny), float(G.sigma));
         dst[4] = make_float4(float(t.w0[0]), float(t.w0[1]), float(t.w0[2]), float(t.wx[0]));
         dst[5] = make_float4(float(t.wx[1]), float(t.wx[2]), float(t.wy[0]), float(t.wy[1]));
-        dst[6] = make_float4(float(t.wy[2]), rgb[0], rgb[1], rgb[2]);
-        dst[7] = make_float4(float(G.sigma), 0.f, 0.f, 0.f);
+        dst[6].x = float(t.wy[2]);
+        dst[7] = make_float4(bbox[0], bbox[1], bbox[2], bbox[3]);
     }
 }
 
-__device__ inline size_t owner_of(const uint32_t* __restrict__ offsets, size_t nslots, uint32_t c) {
-    // Last slot o with offsets[o] <= c (offsets is an exclusive scan).
-    size_t lo = 0, hi = nslots;
-    while (lo < hi) {
-        const size_t mid = (lo + hi) >> 1;
-        if (offsets[mid] <= c) lo = mid + 1;
-        else hi = mid;
+// View-dependent colour of every Gaussian in every view from its SH
+// coefficients (kept apart from k_preprocess so that the 48 coefficients do
+// not occupy registers across the FP64 set-up).  Culled Gaussian-views get a
+// colour too; no list refers to them.
+__global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, float* __restrict__ proj) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const double mu[3] = {double(g.means[i]), double(g.means[g.n + i]), double(g.means[2 * g.n + i])};
+    for (int v = 0; v < views.n; ++v) {
+        const GeoView& V = views.v[v];
+        // Direction from the eye centre o = -R^T t to the mean.
+        double dir[3];
+        for (int c = 0; c < 3; ++c)
+            dir[c] = mu[c] + (double(V.R[c]) * V.t[0] + double(V.R[3 + c]) * V.t[1] + double(V.R[6 + c]) * V.t[2]);
+        const double idn = 1.0 / sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        const float fd[3] = {float(dir[0] * idn), float(dir[1] * idn), float(dir[2] * idn)};
+        float rgb[3];
+        sh_eval(g, i, fd, rgb);
+        float* dst = proj + (size_t(v) * size_t(g.n) + size_t(i)) * kRec + R_RGB;
+        dst[0] = rgb[0];
+        dst[1] = rgb[1];
+        dst[2] = rgb[2];
     }
-    return lo - 1;
 }
 
-// n_inst[0]: candidates (set by the scan), n_inst[1]: kept instances.
-__global__ void __launch_bounds__(256) k_duplicate(GeoViews views, int n, const TileGeo* __restrict__ tgeo,
-                                                   const uint32_t* __restrict__ offsets, size_t nslots,
-                                                   uint32_t* __restrict__ n_inst, uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ gids, size_t capacity) {
-    const size_t total = min(size_t(n_inst[0]), capacity);
-    const size_t stride = size_t(gridDim.x) * blockDim.x;
-    for (size_t base = size_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); base < total; base += stride) {
-        const size_t c = base + (threadIdx.x & 63u);
-        bool kept = false;
-        if (c < total) {
-            const size_t o = owner_of(offsets, nslots, uint32_t(c));
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave per block owns 64 consecutive (view, Gaussian) slots.  It first
+// copies their 64 tile-test records into LDS with coalesced loads, then deals
+// the slots' candidates out to its lanes 64 at a time, so every lane tests
+// one candidate per step whatever the spread of per-Gaussian counts.  The
+// owner of candidate j of the wave is found by a 6-step search of the wave's
+// count prefix in LDS.  n_inst[0]: candidates (from the scan), n_inst[1]:
+// kept instances.
+constexpr int kTgWords = int(sizeof(TileGeo) / 16);  // 16-byte words per record
+
+__global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const TileGeo* __restrict__ tgeo,
+                                                  const uint32_t* __restrict__ offsets,
+                                                  const uint32_t* __restrict__ counts, size_t nslots,
+                                                  uint32_t* __restrict__ n_inst, uint64_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ gids, size_t capacity) {
+    __shared__ uint32_t pre[65];
+    __shared__ TileGeo geo[64];
+    __shared__ GeoView vw[VRS_MAX_VIEWS];
+    const int lane = threadIdx.x;
+    const size_t s0 = size_t(blockIdx.x) * 64;
+    const size_t nown = min(size_t(64), nslots - s0);
+    // The views this block's slots belong to, copied to LDS with uniform
+    // (scalar) reads of the argument table, so lanes of different views
+    // read their constants from LDS.
+    const int v_lo = int(s0 / size_t(n)), v_hi = int((s0 + nown - 1) / size_t(n));
+    for (int v = v_lo; v <= v_hi; ++v)
+        if (lane == 0) vw[v] = views.v[v];
+    const size_t s = s0 + lane;
+    const uint32_t c = s < nslots ? counts[s] : 0u;
+    // Coalesced copy of the block's records: word w of the block's span.
+    {
+        const int4* src = reinterpret_cast<const int4*>(tgeo + s0);
+        int4* dst = reinterpret_cast<int4*>(geo);
+        for (int w = lane; w < int(nown) * kTgWords; w += 64) dst[w] = src[w];
+    }
+    uint32_t incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    pre[lane] = incl - c;
+    if (lane == 63) pre[64] = incl;
+    __syncthreads();
+    const uint32_t total = pre[64];
+    const size_t base = offsets[s0];
+    for (uint32_t j0 = 0; j0 < total; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        bool kept;
+        const size_t cg = base + j;
+        if (j < total && cg < capacity) {
+            int lo = 0, hi = 64;  // last owner l with pre[l] <= j
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[mid] <= j) lo = mid + 1;
+                else hi = mid;
+            }
+            const int ow = lo - 1;
+            const size_t o = s0 + ow;
             const int v = int(o / size_t(n));
             const int i = int(o - size_t(v) * size_t(n));
-            const GeoView& V = views.v[v];
-            const TileGeo& tg = tgeo[o];
-            const int k = int(c - offsets[o]);
+            const GeoView& V = vw[v];
+            const TileGeo& tg = geo[ow];
+            const int k = int(j - pre[ow]);
             const int tx = tg.tx0 + k % tg.ncx, ty = tg.ty0 + k / tg.ncx;
             double bx0, by0, bx1, by1, depth;
             tile_box(V, tx, ty, bx0, by0, bx1, by1);
             kept = tile_test(tg, V, bx0, by0, bx1, by1, &depth);
             const uint64_t tile = uint64_t(V.tile_off) + uint64_t(ty) * V.ntx + tx;
-            keys[c] = kept ? ((tile << 32) | uint64_t(ord_f32(float(depth)))) : ~0ull;
-            gids[c] = uint32_t(i);
+            keys[cg] = kept ? ((tile << 32) | uint64_t(ord_f32(float(depth)))) : ~0ull;
+            gids[cg] = uint32_t(i);
         }
-        const uint64_t b = __ballot(kept);
-        if ((threadIdx.x & 63u) == 0 && b) atomicAdd(&n_inst[1], uint32_t(__popcll(b)));
+    }
+}
+
+// n_inst[1] = number of live (non-dead) keys among the candidates: per-thread
+// counts, one block reduction, one atomic per block.
+__global__ void __launch_bounds__(256) k_count_live(const uint64_t* __restrict__ keys, uint32_t* n_inst,
+                                                    size_t capacity) {
+    __shared__ uint32_t part[4];
+    const size_t total = min(size_t(n_inst[0]), capacity);
+    uint32_t cnt = 0;
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += size_t(gridDim.x) * blockDim.x)
+        cnt += keys[i] != ~0ull ? 1u : 0u;
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t b = part[0] + part[1] + part[2] + part[3];
+        if (b) atomicAdd(&n_inst[1], b);
     }
 }
 
@@ -167,6 +242,7 @@ int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn
     TileGeo* tgeo = reinterpret_cast<TileGeo*>(reinterpret_cast<char*>(proj) + tgeo_offset_bytes(nslots));
     const int blocks = (g.n + 255) / 256;
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, s, g, views, kn, proj, tgeo, counts);
+    hipLaunchKernelGGL(k_color, dim3(blocks), dim3(256), 0, s, g, views, proj);
     return launch_status(hipGetLastError());
 }
 
@@ -183,10 +259,10 @@ int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn,
     if (nslots == 0 || capacity == 0) return launch_status(hipGetLastError());
     const TileGeo* tgeo =
         reinterpret_cast<const TileGeo*>(reinterpret_cast<const char*>(proj) + tgeo_offset_bytes(nslots));
-    size_t blocks = (capacity + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(256), 0, s, views, g.n, tgeo, offsets, nslots, n_inst,
-                       keys, gids, capacity);
+    const size_t blocks = (nslots + 63) / 64;
+    hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(64), 0, s, views, g.n, tgeo, offsets, counts, nslots,
+                       n_inst, keys, gids, capacity);
+    hipLaunchKernelGGL(k_count_live, dim3(256), dim3(256), 0, s, keys, n_inst, capacity);
     return launch_status(hipGetLastError());
 }
 

@@ -166,29 +166,51 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
     const float amax = kn.alpha_max, tmin = kn.t_min;
     uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0;
 
+    // This wave's samples lie in a pixel rectangle; list entries whose box
+    // misses it cannot reach alpha_min at any of them and are skipped for
+    // the whole wave (hierarchical culling of 16x16 subtiles against their
+    // parent's 32x32 list, generalised to every wave).
+    float rx0, ry0, rx1, ry1;
+    if (cls == VRS_CLASS_LOW) {
+        rx0 = float(ox + 1); rx1 = float(ox + 31);
+        ry0 = float(oy + 8 * wv + 1); ry1 = float(oy + 8 * wv + 7);
+    } else {
+        const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
+        rx0 = float(ox + bx) + 0.5f; rx1 = float(ox + bx) + 15.5f;
+        ry0 = float(oy + by + 4 * wv) + 0.5f; ry1 = float(oy + by + 4 * wv) + 3.5f;
+    }
+
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBatch) {
         if (__ballot(acc.alive) == 0ull) break;
         const int nb = int(min(uint32_t(kBatch), rg.y - b0));
-        if (STATS) n_staged += lane < nb ? 1u : 0u;
+        bool rel = false;
         if (lane < nb) {
             const uint32_t gid = gids[b0 + lane];
             const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
-            const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
-            const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
-            // Mean offset relative to the tile origin, split so that the
-            // integer part is exact: (ox - x0i) - x0f.
-            const float ex = float(ox - int(p0.x)) - p0.z;
-            const float ey = float(oy - int(p0.y)) - p0.w;
-            st[lane][0] = make_float4(ex, ey, p1.x, p1.y);          // M00 M01
-            st[lane][1] = make_float4(p1.z, p1.w, p2.x, p2.y);      // M10 M11 a3x a3y
-            st[lane][2] = make_float4(p2.z, p2.w, p3.x, p3.y);      // l2s kap n0 nx
-            st[lane][3] = make_float4(p3.z, p4.x, p4.y, p4.z);      // ny w0
-            st[lane][4] = make_float4(p4.w, p5.x, p5.y, p5.z);      // wx wy.x
-            st[lane][5] = make_float4(p5.w, p6.x, p6.y, p6.z);      // wy.yz r g
-            st[lane][6] = make_float4(p6.w, 0.f, 0.f, 0.f);         // b
+            const float4 p7 = rec[7];
+            rel = !(p7.z < rx0 || p7.x > rx1 || p7.w < ry0 || p7.y > ry1);
+            if (rel) {
+                const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
+                const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
+                // Mean offset relative to the tile origin, split so that the
+                // integer part is exact: (ox - x0i) - x0f.
+                const float ex = float(ox - int(p0.x)) - p0.z;
+                const float ey = float(oy - int(p0.y)) - p0.w;
+                st[lane][0] = make_float4(ex, ey, p1.x, p1.y);          // M00 M01
+                st[lane][1] = make_float4(p1.z, p1.w, p2.x, p2.y);      // M10 M11 a3x a3y
+                st[lane][2] = make_float4(p2.z, p2.w, p3.x, p3.y);      // l2s kap n0 nx
+                st[lane][3] = make_float4(p3.z, p4.x, p4.y, p4.z);      // ny w0
+                st[lane][4] = make_float4(p4.w, p5.x, p5.y, p5.z);      // wx wy.x
+                st[lane][5] = make_float4(p5.w, p6.x, p6.y, p6.z);      // wy.yz r g
+                st[lane][6] = make_float4(p6.w, 0.f, 0.f, 0.f);         // b
+            }
         }
+        uint64_t todo = __ballot(rel);
+        if (STATS) n_staged += uint32_t(__popcll(todo));
         wave_sync_lds();
-        for (int j = 0; j < nb; ++j) {
+        while (todo) {
+            const int j = __builtin_ctzll(todo);
+            todo &= todo - 1;
             const float4 f0 = st[j][0], f1 = st[j][1], f2 = st[j][2];
             const float dx = f0.x + sx, dy = f0.y + sy;
             const float z1 = fmaf(f0.z, dx, f0.w * dy);
@@ -224,11 +246,16 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
     for (int i = 0; i < W; ++i) acc.blend(win.a[i], win.r[i], win.g[i], win.b[i], tmin);
 
     if (STATS) {
-        atomicAdd(&stats[0], (unsigned long long)n_pairs);
-        atomicAdd(&stats[1], (unsigned long long)n_contrib);
-        atomicAdd(&stats[2], (unsigned long long)(inimg ? 1u : 0u));
-        atomicAdd(&stats[3], (unsigned long long)((inimg && !acc.alive) ? 1u : 0u));
-        atomicAdd(&stats[4], (unsigned long long)n_staged);
+        // Wave sums, then one atomic per counter and wave (staged entries are
+        // counted once per wave already).
+        unsigned long long c[4] = {n_pairs, n_contrib, inimg ? 1ull : 0ull, (inimg && !acc.alive) ? 1ull : 0ull};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            for (int d = 32; d >= 1; d >>= 1) c[k] += __shfl_xor(c[k], d);
+        if (lane == 0) {
+            for (int k = 0; k < 4; ++k) atomicAdd(&stats[k], c[k]);
+            atomicAdd(&stats[4], (unsigned long long)n_staged);
+        }
     }
     float o[4] = {acc.cr + acc.T * kn.bg[0], acc.cg + acc.T * kn.bg[1], acc.cb + acc.T * kn.bg[2], 1.f - acc.T};
     float* dst = V.foveated ? V.pre : V.out;

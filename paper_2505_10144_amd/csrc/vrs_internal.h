@@ -25,12 +25,12 @@ enum RecField : int {
     R_L2S = 10,              // log2(opacity)
     R_KAP = 11,              // log2(opacity) - log2(alpha_min): pass iff |z|^2 <= KAP
     R_N0 = 12, R_NX = 13, R_NY = 14,  // depth numerator  n0 + nx dx + ny dy
-    R_SPARE0 = 15,
+    R_SIG = 15,              // opacity
     R_W0 = 16,               // depth denominator |w0 + dx wx + dy wy|^2 (w0: 16..18,
     R_WX = 19, R_WY = 22,    //   wx: 19..21, wy: 22..24)
     R_RGB = 25,              // colour 25..27
-    R_SIG = 28,              // opacity (float)
-    R_SPARE1 = 29, R_SPARE2 = 30, R_SPARE3 = 31,
+    R_BOX = 28,              // pixel box (x0, y0, x1, y1) holding every sample
+                             //   where alpha can reach alpha_min
 };
 
 struct GaussPtrs {
