@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--window", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd leg")
+    ap.add_argument("--diff-steps", type=int, default=10)
     ap.add_argument("--cpu-tiles", type=int, default=24, help="32x32 tiles per eye in the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -111,6 +113,61 @@ def cpu_baseline(scene, cams, fovs, params, n_items, tiles_per_eye):
                    f"with blur neighbours, {samp['stats']['t_shade']:.1f} s on {cores} processes), "
                    f"scaled to the frame: {sec:.0f} s per stereo frame"),
     }
+
+
+def diff_leg(steps, warmup):
+    """fwd+bwd ms per view of the differentiable form: 1M cluster Gaussians,
+    4 plain views at 1024^2, 90-degree FoV.  The upstream gradient is that
+    of L1 + 0.2 L2 against targets rendered (by this renderer) from the
+    scene with perturbed means and opacities; it is computed once before
+    timing (the parameters do not change between timed steps).  A step is
+    one forward render of the 4 views plus vrs_render_backward."""
+    import torch
+    import synth
+    from paper_2505_10144_amd.render import Renderer, upload
+    scene, pert, cams, params = synth.config_diff(0)
+    fovs = [synth.fovea_off()] * len(cams)
+    r = Renderer(cams, fovs, params, scene.n)
+    gp = upload(pert)
+    r.ensure_capacity(gp)
+    targets = [im.clone() for im in r.render(gp)]
+    g = upload(scene)
+    r.ensure_capacity(g)
+    imgs = r.render(g)
+    n = sum(t[:3].numel() for t in targets)
+    dI = []
+    for i, t in zip(imgs, targets):
+        d = torch.zeros_like(i)
+        diff = i[:3] - t[:3]
+        d[:3] = (torch.sign(diff) + 0.4 * diff) / n
+        dI.append(d)
+    for _ in range(warmup):
+        r.render(g)
+        r.backward(g, dI)
+    torch.cuda.synchronize()
+    r.check()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        r.render(g)
+        ev[k][1].record(stream)
+        r.backward(g, dI)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r.check()
+    V = len(cams)
+    fwd = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    bwd = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    ms = (t1 - t0) * 1000.0 / steps
+    return {"ms_per_view": round(ms / V, 4), "fwd_ms_per_view": round(fwd / V, 4),
+            "bwd_ms_per_view": round(bwd / V, 4), "steps": steps, "warmup": warmup,
+            "workload": "differentiation: 1M cluster Gaussians, 4 plain views 1024x1024, 90 deg FoV, "
+                        "tile 16, W=16; dL/dI of L1 + 0.2 L2 against targets of the perturbed scene",
+            "n_gaussians": scene.n, "views": V}
 
 
 def main():
@@ -193,8 +250,11 @@ def main():
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "work": dict(work, candidates=n_cand, instances=n_kept, items=r.n_items),
-        "note": "fwd+bwd ms/view (differentiable form) is not built yet",
     }
+    if not args.no_diff:
+        del r, g
+        torch.cuda.empty_cache()
+        out["fwd_bwd"] = diff_leg(args.diff_steps, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams, fovs, params, r.n_items, args.cpu_tiles)
     print(json.dumps(out), flush=True)

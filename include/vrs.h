@@ -250,6 +250,43 @@ int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uin
                     float* const* rgba, void* ws, size_t ws_bytes, uint64_t* counters_dev,
                     vrs_stream_t stream);
 
+/* Gradients of a scalar loss with respect to the Gaussian parameters, in the
+ * layouts of vrs_gaussians (device memory, FP32, overwritten):
+ *   means[3][n], log_scales[3][n], quats[4][n], opacity_logits[n],
+ *   sh[K][3][n] with K = (sh_degree+1)^2. */
+typedef struct {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+} vrs_gaussian_grads;
+
+/* Workspace bytes of vrs_render_backward: per view and Gaussian, 12 FP32
+ * gradients of the render record. */
+size_t vrs_backward_workspace_size(int32_t n, int32_t n_views);
+
+/* Gradients of the rendered images (Sec. 4.1 fine-tunes position, rotation,
+ * scale, opacity and SH coefficients by backpropagation through the
+ * renderer with StopThePop ordering and Optimal Projection).  Plain views
+ * only: every fovea must have enabled = 0 (else VRS_ERR_UNSUPPORTED).
+ * Inputs: the Gaussians `g`; proj/gids/ranges and rgba[v] from the forward
+ * pass (vrs_preprocess, vrs_sort, vrs_render_foveated) with the same
+ * cameras, foveas and params; grad_rgba[v] = dL/d(rgba[v]), planar
+ * [4][height][width].  The per-sample blending state is recomputed by
+ * replaying the forward (same entries in the same order, same FP32
+ * arithmetic), not stored; a sample's final colour and alpha are read from
+ * rgba[v].  Gradients pass through the windowed order as a fixed
+ * permutation (a discrete decision), and are zero through a clamped alpha
+ * (alpha_max) or a clamped colour (negative SH sum).  Writes every array of
+ * `out` (n Gaussians).  `ws` (16-byte aligned) must hold
+ * vrs_backward_workspace_size(n, n_views) bytes.  Asynchronous on `stream`. */
+int vrs_render_backward(const vrs_gaussians* g, const void* proj, const uint32_t* gids,
+                        const uint32_t* ranges, const vrs_camera* cams, const vrs_fovea* foveas,
+                        int32_t n_views, const vrs_params* p, const float* const* rgba,
+                        const float* const* grad_rgba, const vrs_gaussian_grads* out, void* ws,
+                        size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream);
+
 /* Human-readable name of a status code. */
 const char* vrs_status_string(int code);
 

@@ -210,6 +210,37 @@ def gradients(scene, cams, params, targets, workers=1):
     return float(loss.detach()), grads, res, [i.detach().numpy() for i in imgs]
 
 
+def vjp(scene, cams, params, grad_images, tiles=None, workers=1, mask_flagged=False):
+    """Vector-Jacobian product of the plain-mode renderer: the gradient of
+    sum_v <grad_images[v], I_v> (all four channels) with respect to the raw
+    parameters, for the discrete state of the NumPy forward pass.  With
+    ``tiles`` ({view: [tile ids]}) only those tiles are shaded and replayed,
+    and grad_images is taken as zero elsewhere.  With ``mask_flagged`` it is
+    also taken as zero at pixels the forward pass flags as borderline (a
+    near-tie that may order or cut differently in another precision).
+    Returns (grads dict, forward result dict, the grad_images used)."""
+    opts = OracleOptions(record=True, workers=workers, tiles=tiles)
+    res = render_full(scene, cams, _plain(cams), params, opts)
+    used = []
+    for v, gi in enumerate(grad_images):
+        gi = np.array(gi, np.float64, copy=True)
+        keep = res["valid"][v].copy()
+        if mask_flagged:
+            keep &= ~res["flags"][v]
+        gi[:, ~keep] = 0.0
+        used.append(gi)
+    grad_images = used
+    lists = emission_lists(res, cams)
+    ts = [torch.tensor(np.asarray(a, np.float64), dtype=DT, requires_grad=True)
+          for a in (scene.means, scene.log_scales, scene.quats, scene.opacity_logits, scene.sh)]
+    imgs = replay(ts, scene.sh_degree, cams, params, lists)
+    total = sum((torch.tensor(np.asarray(gi, np.float64), dtype=DT) * im).sum()
+                for gi, im in zip(grad_images, imgs))
+    total.backward()
+    names = ("means", "log_scales", "quats", "opacity_logits", "sh")
+    return {n: t.grad.numpy().copy() for n, t in zip(names, ts)}, res, used
+
+
 def _plain(cams):
     from synth import fovea_off
     return [fovea_off() for _ in cams]

@@ -5,13 +5,16 @@ per-sample resorting, all in hand-written HIP kernels behind the C ABI of
 include/vrs.h.  Importing the package loads nothing; the HIP library is loaded
 on first use and its absence is an error (there is no other compute path)."""
 
-__all__ = ["Renderer", "Gaussians", "upload", "build", "lib"]
+__all__ = ["Renderer", "Gaussians", "upload", "rasterize", "build", "lib"]
 
 
 def __getattr__(name):
     if name in ("Renderer", "Gaussians", "upload"):
         from . import render
         return getattr(render, name)
+    if name == "rasterize":
+        from .autograd import rasterize
+        return rasterize
     if name == "build":
         from .build import build
         return build

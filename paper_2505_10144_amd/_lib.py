@@ -58,6 +58,12 @@ class vrs_sizes(ctypes.Structure):
                 ("render_ws_bytes", ctypes.c_size_t)]
 
 
+class vrs_gaussian_grads(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacity_logits", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p)]
+
+
 # Every function the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
@@ -89,6 +95,11 @@ SIGNATURES = {
                              _P]),
     "vrs_compose": (_I, [ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params),
                          _P, ctypes.POINTER(ctypes.c_void_p), _P, _S, _P]),
+    "vrs_backward_workspace_size": (_S, [_I, _I]),
+    "vrs_render_backward": (_I, [ctypes.POINTER(vrs_gaussians), _P, _P, _P, ctypes.POINTER(vrs_camera),
+                                 ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params),
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                 ctypes.POINTER(vrs_gaussian_grads), _P, _S, _P, _P]),
     "vrs_status_string": (ctypes.c_char_p, [_I]),
     "vrs_version": (ctypes.c_char_p, []),
 }

@@ -449,3 +449,68 @@ int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const
 }
 
 }  // extern "C"
+
+namespace vrs {
+size_t backward_ws_bytes(size_t n, int n_views);
+int launch_backward(const GaussPtrs&, const GeoViews&, const float*, const uint32_t*, const uint32_t*,
+                    const BwdViews&, const Knobs&, int, float*, const GradPtrs&, hipStream_t);
+}  // namespace vrs
+
+extern "C" {
+
+size_t vrs_backward_workspace_size(int32_t n, int32_t n_views) {
+    if (n < 0 || n_views < 0) return 0;
+    return vrs::backward_ws_bytes(size_t(n), n_views);
+}
+
+int vrs_render_backward(const vrs_gaussians* g, const void* proj, const uint32_t* gids, const uint32_t* ranges,
+                        const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,
+                        const float* const* rgba, const float* const* grad_rgba, const vrs_gaussian_grads* out,
+                        void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream) {
+    (void)status_dev;
+    int rc = check_gaussians(g);
+    if (rc != VRS_OK) return rc;
+    Layout L;
+    rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    for (int v = 0; v < n_views; ++v)
+        if (foveas[v].enabled) return VRS_ERR_UNSUPPORTED;
+    if (!rgba || !grad_rgba || !out) return VRS_ERR_INVALID_ARG;
+    if (g->n > 0) {
+        if (!proj || !gids || !ranges || !aligned(proj, 16)) return VRS_ERR_INVALID_ARG;
+        if (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh)
+            return VRS_ERR_INVALID_ARG;
+        if (!ws || !aligned(ws, 16) || ws_bytes < backward_ws_bytes(size_t(g->n), n_views))
+            return VRS_ERR_INVALID_ARG;
+    }
+    BwdViews B;
+    memset(&B, 0, sizeof(B));
+    B.n = n_views;
+    uint32_t items = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (!rgba[v] || !grad_rgba[v]) return VRS_ERR_INVALID_ARG;
+        const ViewLayout& V = L.v[v];
+        BwdView& o = B.v[v];
+        o.rgba = rgba[v];
+        o.grad = grad_rgba[v];
+        o.W = cams[v].width;
+        o.H = cams[v].height;
+        o.T = V.T;
+        o.ntx = V.ntx;
+        o.tile_off = V.tile_off;
+        o.item_off = items;
+        items += uint32_t(V.ntx * V.nty) * (V.T == 32 ? 4u : 1u);
+    }
+    B.items_total = items;
+    GradPtrs G;
+    G.means = out->means;
+    G.log_scales = out->log_scales;
+    G.quats = out->quats;
+    G.opac = out->opacity_logits;
+    G.sh = out->sh;
+    return launch_backward(gauss_ptrs(g), geo_views(cams, L, p), static_cast<const float*>(proj), gids, ranges, B,
+                           knobs(p), p->window, static_cast<float*>(ws), G,
+                           reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,657 @@
+// K8: gradients of the rendered images with respect to the Gaussian
+// parameters (Sec. 4.1: the Gaussians are fine-tuned by backpropagation
+// through the StopThePop-ordered, Optimal-Projection renderer), for plain
+// (non-foveated) views.
+//
+// K8a (k_render_bwd) replays, per sample, the forward blending of k_render:
+// the same list order, box culling, alpha test, resort window and stop rule
+// in the same FP32 arithmetic, so it emits the same entries in the same
+// order.  Nothing per sample is stored by the forward pass; the replay needs
+// only the forward's final colour and transmittance (read back from the
+// output image).  At the i-th blended entry it knows T_i and the colour
+// accumulated so far, and forms
+//   dL/dc_i     = g_rgb alpha_i T_i
+//   dL/dalpha_i = g_rgb . (c_i T_i - S_i / (1 - alpha_i)) + g_a T_fin / (1 - alpha_i),
+//   S_i         = (C_fin - C_<=i) + background T_fin   (the colour behind i),
+// then chains dL/dalpha through alpha = opacity 2^(-|z|^2 / h^2) to the 12
+// per-view splat parameters of the render record (M, a3, mean image point,
+// opacity, RGB).  The window holds (depth, alpha, arrival index).  The
+// records of the last four staged batches stay in a block-shared LDS ring
+// beside their gradient accumulators; a batch's sums go to the per-view
+// [Gaussian][12] buffer with one global atomic per value when the batch
+// leaves the ring.  A window entry emitted after its batch left the ring is
+// re-read from HBM and accumulated with global atomics.  When every emitting
+// lane of a wave emits the same entry (the common case), the wave sums the
+// 12 values first and one lane adds them.
+//
+// K8b (k_color_bwd, k_geom_bwd) chains the per-view splat gradients to the
+// raw parameters (means, log-scales, quaternions, opacity logits, SH), one
+// thread per Gaussian: the set-up geometry of K1 and the SH colour are
+// re-evaluated in FP64 forward-mode dual numbers, one pass per parameter
+// they depend on, which gives exact derivatives of the formulas K1 uses.
+#include <float.h>
+
+#include "geom.h"
+
+namespace vrs {
+
+constexpr int kBwdThreads = 256;
+constexpr int kBwdBatch = 64;  // entries staged per batch (one per lane of a wave)
+constexpr int kRingBatches = 4;
+constexpr int kRing = kBwdBatch * kRingBatches;
+constexpr int kG = 12;  // gradient values per (view, Gaussian)
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Gradient slots of one (view, Gaussian).
+enum GradField : int {
+    G_M = 0,    // dL/dM00, M01, M10, M11 of the render record
+    G_A3 = 4,   // dL/da3x, a3y
+    G_XY = 6,   // dL/d(mean image point x, y)
+    G_SIG = 8,  // dL/dopacity
+    G_RGB = 9,  // dL/dcolour r, g, b
+};
+
+template <int W>
+struct BWindow {
+    float t[W], a[W];
+    uint32_t k[W];
+
+    __device__ inline void init() {
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            t[i] = -FLT_MAX;
+            a[i] = 0.f;
+            k[i] = kNone;
+        }
+    }
+    // The forward window's insertion network (see k_render): inserts x and
+    // returns the entry with the smallest depth among the window and x.
+    __device__ inline void push(float xt, float xa, uint32_t xk, float& ea, uint32_t& ek) {
+        bool c[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) c[i] = t[i] <= xt;
+        ea = c[0] ? a[0] : xa;
+        ek = c[0] ? k[0] : xk;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            t[i] = c[i] ? xt : t[i];
+            a[i] = c[i] ? xa : a[i];
+            k[i] = c[i] ? xk : k[i];
+            if (i + 1 < W) {
+                t[i] = c[i + 1] ? t[i + 1] : t[i];
+                a[i] = c[i + 1] ? a[i + 1] : a[i];
+                k[i] = c[i + 1] ? k[i + 1] : k[i];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // Remove slot 0 (the smallest depth); the last slot becomes empty.
+    __device__ inline void shift() {
+#pragma unroll
+        for (int i = 0; i + 1 < W; ++i) {
+            t[i] = t[i + 1];
+            a[i] = a[i + 1];
+            k[i] = k[i + 1];
+        }
+        t[W - 1] = -FLT_MAX;
+        a[W - 1] = 0.f;
+        k[W - 1] = kNone;
+    }
+};
+
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    return x;
+}
+
+// Staged form of one list entry (7 float4, as in k_render): tile-relative
+// mean offset, M, a3, log2 opacity, KAP, depth coefficients, colour.
+__device__ inline void stage_entry(const float4* rec, int ox, int oy, float4 out[7]) {
+    const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
+    const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
+    out[0] = make_float4(float(ox - int(p0.x)) - p0.z, float(oy - int(p0.y)) - p0.w, p1.x, p1.y);
+    out[1] = make_float4(p1.z, p1.w, p2.x, p2.y);
+    out[2] = make_float4(p2.z, p2.w, p3.x, p3.y);
+    out[3] = make_float4(p3.z, p4.x, p4.y, p4.z);
+    out[4] = make_float4(p4.w, p5.x, p5.y, p5.z);
+    out[5] = make_float4(p5.w, p6.x, p6.y, p6.z);
+    out[6] = make_float4(p6.w, 0.f, 0.f, 0.f);
+}
+
+template <int W>
+__global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restrict__ proj, uint32_t n_gauss,
+                                                            const uint32_t* __restrict__ gids,
+                                                            const uint32_t* __restrict__ ranges, BwdViews views,
+                                                            Knobs kn, float* __restrict__ grad2d) {
+    __shared__ float4 ring[kRing][7];
+    __shared__ float4 ring_box[kRing];
+    __shared__ float acc[kRing][kG];
+    __shared__ uint32_t ring_gid[kRing];
+
+    const uint32_t item = blockIdx.x;
+    int v = 0;
+    while (v + 1 < views.n && item >= views.v[v + 1].item_off) ++v;
+    const BwdView& V = views.v[v];
+    const int T = V.T;
+    const uint32_t local = item - V.item_off;
+    const uint32_t tile = (T == 32) ? local >> 2 : local;
+    const int sub = (T == 32) ? int(local & 3u) : 0;
+    const int tx = int(tile % uint32_t(V.ntx)), ty = int(tile / uint32_t(V.ntx));
+    const int ox = tx * T, oy = ty * T;
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    // Sample of this thread: the forward's quad-major 16x16 layout.
+    const int qd = t >> 2, kq = t & 3;
+    const int lx = 2 * (qd & 7) + (kq & 1), ly = 2 * (qd >> 3) + (kq >> 1);
+    const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
+    const int px = ox + bx + lx, py = oy + by + ly;
+    const float sx = float(bx + lx) + 0.5f, sy = float(by + ly) + 0.5f;
+    const bool inimg = px < V.W && py < V.H;
+
+    // Forward final state and the incoming gradient of this sample.
+    const size_t plane = size_t(V.W) * size_t(V.H);
+    float gr[3] = {0.f, 0.f, 0.f}, ga = 0.f, Cf[3] = {0.f, 0.f, 0.f}, Tf = 1.f;
+    if (inimg) {
+        const size_t pix = size_t(py) * V.W + px;
+        Tf = 1.f - V.rgba[3 * plane + pix];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gr[c] = V.grad[c * plane + pix];
+            Cf[c] = V.rgba[c * plane + pix] - Tf * kn.bg[c];
+        }
+        ga = V.grad[3 * plane + pix];
+    }
+    // The part of dL/dalpha_i (times 1 - alpha_i) that does not depend on i.
+    const float gback = (ga - (gr[0] * kn.bg[0] + gr[1] * kn.bg[1] + gr[2] * kn.bg[2])) * Tf;
+
+    float Tc = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    bool alive = inimg;
+    BWindow<W> win;
+    win.init();
+    const float amax = kn.alpha_max, tmin = kn.t_min;
+
+    const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
+    const uint32_t L = rg.y - rg.x;
+    const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
+    float* vgrad = grad2d + size_t(v) * size_t(n_gauss) * kG;
+    const float rx0 = float(ox + bx) + 0.5f, rx1 = float(ox + bx) + 15.5f;
+    const float ry0 = float(oy + by + 4 * wv) + 0.5f, ry1 = float(oy + by + 4 * wv) + 3.5f;
+    uint32_t ring_lo = 0;  // smallest arrival index whose record is still in the ring
+
+    // Blend the entry leaving the window (alpha ea, arrival index ek) and
+    // accumulate its gradient.  Called at wave-uniform points.
+    auto emit = [&](float ea, uint32_t ek) {
+        bool valid = alive && ek != kNone;
+        const float Tn = Tc * (1.f - ea);
+        if (valid && Tn < tmin) {  // stops the sample; not blended
+            alive = false;
+            valid = false;
+        }
+        const uint64_t vm = __ballot(valid);
+        if (vm == 0ull) return;
+        float g[kG];
+#pragma unroll
+        for (int k = 0; k < kG; ++k) g[k] = 0.f;
+        const bool in_ring = ek >= ring_lo;
+        const int sl = int(ek % uint32_t(kRing));
+        uint32_t gid = 0;
+        if (valid) {
+            float4 e[7];
+            if (in_ring) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) e[k] = ring[sl][k];
+                gid = ring_gid[sl];
+            } else {
+                gid = gids[rg.x + ek];
+                stage_entry(reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec), ox, oy, e);
+            }
+            const float cr = e[5].z, cg = e[5].w, cb = e[6].x;
+            const float w = Tc * ea;
+            const float n0 = fmaf(w, cr, C0), n1 = fmaf(w, cg, C1), n2 = fmaf(w, cb, C2);
+            const float inv1 = 1.f / (1.f - ea);
+            float dA = gr[0] * (cr * Tc - (Cf[0] - n0) * inv1);
+            dA = fmaf(gr[1], cg * Tc - (Cf[1] - n1) * inv1, dA);
+            dA = fmaf(gr[2], cb * Tc - (Cf[2] - n2) * inv1, dA);
+            dA = fmaf(gback, inv1, dA);
+            g[G_RGB] = gr[0] * w;
+            g[G_RGB + 1] = gr[1] * w;
+            g[G_RGB + 2] = gr[2] * w;
+            // alpha = opacity 2^(-E), E = q / h^2, q = |M delta|^2, delta =
+            // sample - mean; a clamped alpha passes no gradient to the splat.
+            const float dx = e[0].x + sx, dy = e[0].y + sy;
+            const float M00 = e[0].z, M01 = e[0].w, M10 = e[1].x, M11 = e[1].y;
+            const float a3x = e[1].z, a3y = e[1].w;
+            const float z1 = fmaf(M00, dx, M01 * dy);
+            const float z2 = fmaf(M10, dx, M11 * dy);
+            const float h = fmaf(a3x, dx, fmaf(a3y, dy, 1.f));
+            const float q = fmaf(z1, z1, z2 * z2);
+            const float ih = 1.f / h;
+            const float ih2 = ih * ih;
+            const float E = q * ih2;
+            const float a_un = exp2f(e[2].x - E);  // unclamped alpha
+            if (a_un < amax) {
+                const float gE = dA * (-0.69314718055994531f) * a_un;  // dL/dE
+                const float cz = 2.f * gE * ih2;
+                const float ch = -2.f * gE * E * ih;
+                g[G_M + 0] = cz * z1 * dx;
+                g[G_M + 1] = cz * z1 * dy;
+                g[G_M + 2] = cz * z2 * dx;
+                g[G_M + 3] = cz * z2 * dy;
+                g[G_A3 + 0] = ch * dx;
+                g[G_A3 + 1] = ch * dy;
+                g[G_XY + 0] = -(cz * fmaf(z1, M00, z2 * M10) + ch * a3x);
+                g[G_XY + 1] = -(cz * fmaf(z1, M01, z2 * M11) + ch * a3y);
+                g[G_SIG] = dA * exp2f(-E);
+            }
+            C0 = n0;
+            C1 = n1;
+            C2 = n2;
+            Tc = Tn;
+        }
+        const int l0 = __builtin_ctzll(vm);
+        const uint32_t k0 = __shfl(ek, l0);
+        if (__ballot(valid && ek != k0) == 0ull) {
+            // One entry for the whole wave: reduce, then one lane adds.
+#pragma unroll
+            for (int k = 0; k < kG; ++k) g[k] = wave_sum(g[k]);
+            if (lane == l0) {
+                if (in_ring) {
+#pragma unroll
+                    for (int k = 0; k < kG; ++k) atomicAdd(&acc[sl][k], g[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kG; ++k) unsafeAtomicAdd(&vgrad[size_t(gid) * kG + k], g[k]);
+                }
+            }
+        } else if (valid) {
+            if (in_ring) {
+#pragma unroll
+                for (int k = 0; k < kG; ++k) atomicAdd(&acc[sl][k], g[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < kG; ++k) unsafeAtomicAdd(&vgrad[size_t(gid) * kG + k], g[k]);
+            }
+        }
+    };
+
+    uint32_t last_b0 = 0, staged_end = 0;
+    for (uint32_t b0 = 0; b0 < L; b0 += kBwdBatch) {
+        // The forward stops a wave once all its samples have stopped; the
+        // block stops when all four waves have.
+        if (__syncthreads_or(alive ? 1 : 0) == 0) break;
+        const int nb = int(min(uint32_t(kBwdBatch), L - b0));
+        const int base = int(b0 % uint32_t(kRing));
+        if (b0 >= uint32_t(kRing)) {
+            // Flush the batch that leaves the ring.
+            for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
+                const int s = base + w / kG, k = w % kG;
+                const float val = acc[s][k];
+                if (val != 0.f) unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], val);
+            }
+            __syncthreads();
+            ring_lo = b0 + kBwdBatch - kRing;
+        }
+        if (t < nb) {
+            const uint32_t gid = gids[rg.x + b0 + t];
+            const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
+            float4 e[7];
+            stage_entry(rec, ox, oy, e);
+#pragma unroll
+            for (int k = 0; k < 7; ++k) ring[base + t][k] = e[k];
+            ring_box[base + t] = rec[7];
+            ring_gid[base + t] = gid;
+        }
+        for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) acc[base + w / kG][w % kG] = 0.f;
+        last_b0 = b0;
+        staged_end = b0 + uint32_t(nb);
+        __syncthreads();
+        bool rel = false;
+        if (lane < nb) {
+            const float4 bb = ring_box[base + lane];
+            rel = !(bb.z < rx0 || bb.x > rx1 || bb.w < ry0 || bb.y > ry1);
+        }
+        uint64_t todo = __ballot(rel);
+        if (__ballot(alive) == 0ull) todo = 0ull;
+        while (todo) {
+            const int j = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const float4* st = ring[base + j];
+            const float4 f0 = st[0], f1 = st[1], f2 = st[2];
+            const float dx = f0.x + sx, dy = f0.y + sy;
+            const float z1 = fmaf(f0.z, dx, f0.w * dy);
+            const float z2 = fmaf(f1.x, dx, f1.y * dy);
+            const float h = fmaf(f1.z, dx, fmaf(f1.w, dy, 1.f));
+            const float q = fmaf(z1, z1, z2 * z2);
+            const float h2 = h * h;
+            const bool pass = alive && (h > 0.f) && (q <= f2.y * h2);
+            if (__ballot(pass) != 0ull) {  // wave-uniform
+                const float4 f3 = st[3], f4 = st[4], f5 = st[5];
+                const float xa = pass ? fminf(amax, exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2))) : 0.f;
+                const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
+                const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
+                const float w1 = fmaf(f4.y, dx, fmaf(f5.x, dy, f3.z));
+                const float w2 = fmaf(f4.z, dx, fmaf(f5.y, dy, f3.w));
+                const float den = fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
+                const float xt = pass ? num * __builtin_amdgcn_rcpf(den) : -INFINITY;
+                float ea;
+                uint32_t ek;
+                win.push(xt, xa, pass ? b0 + uint32_t(j) : kNone, ea, ek);
+                emit(ea, ek);
+            }
+            if (__ballot(alive) == 0ull) break;
+        }
+    }
+    // Flush the window in ascending depth order.
+#pragma unroll 1
+    for (int i = 0; i < W; ++i) {
+        const float ea = win.a[0];
+        const uint32_t ek = win.k[0];
+        win.shift();
+        emit(ea, ek);
+    }
+    __syncthreads();
+    // Flush what is left in the ring: arrival indices [first, staged_end).
+    const uint32_t span = uint32_t(kRing - kBwdBatch);
+    const uint32_t first = last_b0 >= span ? last_b0 - span : 0u;
+    for (int w = t; w < kRing * kG; w += kBwdThreads) {
+        const int s = w / kG, k = w % kG;
+        const uint32_t a = first + (uint32_t(s) + uint32_t(kRing) - first % uint32_t(kRing)) % uint32_t(kRing);
+        if (a >= staged_end) continue;
+        const float val = acc[s][k];
+        if (val != 0.f) unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], val);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K8b: FP64 forward-mode dual numbers.
+// ---------------------------------------------------------------------------
+struct Dual {
+    double v, d;
+};
+__device__ inline Dual dconst(double x) { return Dual{x, 0.0}; }
+__device__ inline Dual operator+(Dual a, Dual b) { return Dual{a.v + b.v, a.d + b.d}; }
+__device__ inline Dual operator-(Dual a, Dual b) { return Dual{a.v - b.v, a.d - b.d}; }
+__device__ inline Dual operator-(Dual a) { return Dual{-a.v, -a.d}; }
+__device__ inline Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, a.v * b.d + a.d * b.v}; }
+__device__ inline Dual operator*(double a, Dual b) { return Dual{a * b.v, a * b.d}; }
+__device__ inline Dual operator+(double a, Dual b) { return Dual{a + b.v, b.d}; }
+__device__ inline Dual operator-(double a, Dual b) { return Dual{a - b.v, -b.d}; }
+__device__ inline Dual operator/(Dual a, Dual b) {
+    const double iv = 1.0 / b.v;
+    const double q = a.v * iv;
+    return Dual{q, (a.d - q * b.d) * iv};
+}
+__device__ inline Dual dsqrt(Dual a) {
+    const double s = sqrt(a.v);
+    return Dual{s, a.d * (0.5 / s)};
+}
+__device__ inline Dual dexp(Dual a) {
+    const double e = exp(a.v);
+    return Dual{e, a.d * e};
+}
+
+// M (with the record's power-of-two scale), a3 and the mean's image point
+// as functions of the mean, log-scales and quaternion: the formulas of
+// load_gaussian and make_geo, in dual arithmetic.
+__device__ inline void splat_params(const Dual mu[3], const Dual ls[3], const Dual q[4], const GeoView& V,
+                                    double dil, Dual M[4], Dual a3[2], Dual xy[2]) {
+    const Dual qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    const Dual k2 = dconst(2.0) / qq;
+    const Dual w = q[0], x = q[1], y = q[2], z = q[3];
+    Dual R[9];
+    R[0] = 1.0 - k2 * (y * y + z * z);
+    R[1] = k2 * (x * y - w * z);
+    R[2] = k2 * (x * z + w * y);
+    R[3] = k2 * (x * y + w * z);
+    R[4] = 1.0 - k2 * (x * x + z * z);
+    R[5] = k2 * (y * z - w * x);
+    R[6] = k2 * (x * z - w * y);
+    R[7] = k2 * (y * z + w * x);
+    R[8] = 1.0 - k2 * (x * x + y * y);
+    Dual s[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] = dexp(ls[c]);
+    double Rv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rv[k] = double(V.R[k]);
+    Dual muc[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        muc[r] = Rv[3 * r] * mu[0] + Rv[3 * r + 1] * mu[1] + Rv[3 * r + 2] * mu[2] + dconst(double(V.t[r]));
+    const Dual rr = dsqrt(muc[0] * muc[0] + muc[1] * muc[1] + muc[2] * muc[2]);
+    const Dual ux = muc[0] / rr, uy = muc[1] / rr, uz = muc[2] / rr;
+    const Dual kk = dconst(1.0) / (1.0 + uz);
+    const Dual e1[3] = {1.0 - ux * ux * kk, -(ux * uy * kk), -ux};
+    const Dual e2[3] = {-(ux * uy * kk), 1.0 - uy * uy * kk, -uy};
+    // G2 = E^T R_c S with R_c = R_v R.
+    Dual g0[3], g1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const Dual c0 = Rv[0] * R[c] + Rv[1] * R[3 + c] + Rv[2] * R[6 + c];
+        const Dual c1 = Rv[3] * R[c] + Rv[4] * R[3 + c] + Rv[5] * R[6 + c];
+        const Dual c2 = Rv[6] * R[c] + Rv[7] * R[3 + c] + Rv[8] * R[6 + c];
+        g0[c] = (e1[0] * c0 + e1[1] * c1 + e1[2] * c2) * s[c];
+        g1[c] = (e2[0] * c0 + e2[1] * c1 + e2[2] * c2) * s[c];
+    }
+    const Dual fr = dconst(V.f) / rr;
+    const Dual sc = fr * fr;
+    const Dual sa = sc * (g0[0] * g0[0] + g0[1] * g0[1] + g0[2] * g0[2]) + dconst(dil);
+    const Dual sb = sc * (g0[0] * g1[0] + g0[1] * g1[1] + g0[2] * g1[2]);
+    const Dual scc = sc * (g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]) + dconst(dil);
+    const Dual det = sa * scc - sb * sb;
+    const Dual c00 = scc / det, c01 = -(sb / det), c11 = sa / det;
+    const Dual l00 = dsqrt(c00);
+    const Dual l01 = c01 / l00;
+    const Dual l11 = dsqrt(c11 - l01 * l01);
+    const double zs = double(float(sqrt(0.5 / M_LN2)));  // the record's scale, as rounded there
+    M[0] = zs * (uz * (l00 * e1[0] + l01 * e2[0]));
+    M[1] = zs * (uz * (l00 * e1[1] + l01 * e2[1]));
+    M[2] = zs * (uz * (l11 * e2[0]));
+    M[3] = zs * (uz * (l11 * e2[1]));
+    a3[0] = V.inv_f * (uz * ux);
+    a3[1] = V.inv_f * (uz * uy);
+    xy[0] = double(V.cx) + V.f * (muc[0] / muc[2]);
+    xy[1] = double(V.cy) + V.f * (muc[1] / muc[2]);
+}
+
+// Real SH basis (the polynomials of sh_eval) at a dual unit direction.
+__device__ inline void sh_basis_dual(int K, const Dual v[3], Dual Y[16]) {
+    const Dual x = v[0], y = v[1], z = v[2];
+    constexpr double pi = M_PI;
+    Y[0] = dconst(0.5 / sqrt(pi));
+    if (K > 1) {
+        const double c1 = sqrt(3.0 / (4.0 * pi));
+        Y[1] = -(c1 * y);
+        Y[2] = c1 * z;
+        Y[3] = -(c1 * x);
+    }
+    if (K > 4) {
+        const double c2a = sqrt(15.0 / (4.0 * pi)), c2b = sqrt(5.0 / (16.0 * pi)), c2c = sqrt(15.0 / (16.0 * pi));
+        Y[4] = c2a * (x * y);
+        Y[5] = -(c2a * (y * z));
+        Y[6] = c2b * (3.0 * (z * z) - dconst(1.0));
+        Y[7] = -(c2a * (x * z));
+        Y[8] = c2c * (x * x - y * y);
+    }
+    if (K > 9) {
+        const double c3a = sqrt(35.0 / (32.0 * pi)), c3b = sqrt(105.0 / (4.0 * pi));
+        const double c3c = sqrt(21.0 / (32.0 * pi)), c3d = sqrt(7.0 / (16.0 * pi));
+        const double c3e = sqrt(105.0 / (16.0 * pi));
+        const Dual xx = x * x, yy = y * y, zz = z * z;
+        Y[9] = -(c3a * (y * (3.0 * xx - yy)));
+        Y[10] = c3b * (x * y * z);
+        Y[11] = -(c3c * (y * (5.0 * zz - dconst(1.0))));
+        Y[12] = c3d * (z * (5.0 * zz - dconst(3.0)));
+        Y[13] = -(c3c * (x * (5.0 * zz - dconst(1.0))));
+        Y[14] = c3e * (z * (xx - yy));
+        Y[15] = -(c3a * (x * (xx - 3.0 * yy)));
+    }
+}
+
+// Gradient of one Gaussian's render-record gradients of view v (12 floats).
+__device__ inline void load_g12(const float* grad2d, int v, int n, int i, float gv[kG]) {
+    const float4* gg = reinterpret_cast<const float4*>(grad2d + (size_t(v) * n + i) * kG);
+    const float4 a = gg[0], b = gg[1], c = gg[2];
+    gv[0] = a.x; gv[1] = a.y; gv[2] = a.z; gv[3] = a.w;
+    gv[4] = b.x; gv[5] = b.y; gv[6] = b.z; gv[7] = b.w;
+    gv[8] = c.x; gv[9] = c.y; gv[10] = c.z; gv[11] = c.w;
+}
+
+// K8b, colour part: SH coefficients, and the mean through the view
+// direction.  Writes out.sh and out.means (the geometry part adds to the
+// latter).
+__global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, const float* __restrict__ grad2d,
+                                                   GradPtrs out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int n = g.n;
+    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    const double mu[3] = {double(g.means[i]), double(g.means[n + i]), double(g.means[2 * n + i])};
+    float gsh[16][3];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+    double gm[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < views.n; ++v) {
+        const GeoView& V = views.v[v];
+        const float4 gc = reinterpret_cast<const float4*>(grad2d + (size_t(v) * n + i) * kG)[2];
+        const float grgb[3] = {gc.y, gc.z, gc.w};
+        if (grgb[0] == 0.f && grgb[1] == 0.f && grgb[2] == 0.f) continue;
+        // colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = unit vector from
+        // the eye centre o = -R^T t to the mean.
+        double dir[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            dir[c] = mu[c] + (double(V.R[c]) * V.t[0] + double(V.R[3 + c]) * V.t[1] + double(V.R[6 + c]) * V.t[2]);
+#pragma unroll 1
+        for (int pi = 0; pi < 3; ++pi) {
+            Dual d[3];
+            for (int c = 0; c < 3; ++c) d[c] = Dual{dir[c], pi == c ? 1.0 : 0.0};
+            const Dual dn = dsqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const Dual u[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+            Dual Y[16];
+            sh_basis_dual(K, u, Y);
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                Dual col = dconst(0.5);
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if (k < K) col = col + double(g.sh[(k * 3 + c) * n + i]) * Y[k];
+                if (col.v > 0.0) {  // a clamped colour passes no gradient
+                    s += double(grgb[c]) * col.d;
+                    if (pi == 0) {
+#pragma unroll
+                        for (int k = 0; k < 16; ++k)
+                            if (k < K) gsh[k][c] += grgb[c] * float(Y[k].v);
+                    }
+                }
+            }
+            gm[pi] += s;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.means[c * n + i] = float(gm[c]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (k < K)
+            for (int c = 0; c < 3; ++c) out.sh[(k * 3 + c) * n + i] = gsh[k][c];
+}
+
+// K8b, geometry part: means (added to the colour part), log-scales,
+// quaternions and opacity logits.
+__global__ void __launch_bounds__(128) k_geom_bwd(GaussPtrs g, GeoViews views, Knobs kn,
+                                                  const float* __restrict__ grad2d, GradPtrs out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    const int n = g.n;
+    double p[10];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[c] = double(g.means[c * n + i]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[3 + c] = double(g.log_scales[c * n + i]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) p[6 + c] = double(g.quats[c * n + i]);
+    const double sig = 1.0 / (1.0 + exp(-double(g.opac[i])));
+    double gp[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) gp[k] = 0.0;
+    double gop = 0.0;
+    for (int v = 0; v < views.n; ++v) {
+        const GeoView& V = views.v[v];
+        float gv[kG];
+        load_g12(grad2d, v, n, i, gv);
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < G_RGB; ++k) any = any || gv[k] != 0.f;
+        if (!any) continue;
+        gop += double(gv[G_SIG]) * sig * (1.0 - sig);
+        // One dual pass per mean, log-scale and quaternion entry.
+#pragma unroll 1
+        for (int pi = 0; pi < 10; ++pi) {
+            Dual mu[3], ls[3], q[4];
+            for (int c = 0; c < 3; ++c) {
+                mu[c] = Dual{p[c], pi == c ? 1.0 : 0.0};
+                ls[c] = Dual{p[3 + c], pi == 3 + c ? 1.0 : 0.0};
+            }
+            for (int c = 0; c < 4; ++c) q[c] = Dual{p[6 + c], pi == 6 + c ? 1.0 : 0.0};
+            Dual M[4], a3[2], xy[2];
+            splat_params(mu, ls, q, V, double(kn.dilation), M, a3, xy);
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s += double(gv[G_M + k]) * M[k].d;
+            s += double(gv[G_A3]) * a3[0].d + double(gv[G_A3 + 1]) * a3[1].d;
+            s += double(gv[G_XY]) * xy[0].d + double(gv[G_XY + 1]) * xy[1].d;
+            gp[pi] += s;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.means[c * n + i] = float(double(out.means[c * n + i]) + gp[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.log_scales[c * n + i] = float(gp[3 + c]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out.quats[c * n + i] = float(gp[6 + c]);
+    out.opac[i] = float(gop);
+}
+
+__global__ void __launch_bounds__(256) k_fill_f32(float* __restrict__ p, size_t n) {
+    const size_t stride = size_t(gridDim.x) * blockDim.x;
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.f;
+}
+
+size_t backward_ws_bytes(size_t n, int n_views) { return n * size_t(n_views) * kG * sizeof(float); }
+
+template <int W>
+static void launch_render_bwd(const float* proj, uint32_t n, const uint32_t* gids, const uint32_t* ranges,
+                              const BwdViews& views, const Knobs& kn, float* grad2d, hipStream_t s) {
+    hipLaunchKernelGGL(k_render_bwd<W>, dim3(views.items_total), dim3(kBwdThreads), 0, s, proj, n, gids, ranges,
+                       views, kn, grad2d);
+}
+
+int launch_backward(const GaussPtrs& g, const GeoViews& gv, const float* proj, const uint32_t* gids,
+                    const uint32_t* ranges, const BwdViews& views, const Knobs& kn, int window, float* grad2d,
+                    const GradPtrs& out, hipStream_t s) {
+    const size_t ng = size_t(g.n) * size_t(views.n) * kG;
+    if (ng > 0) {
+        const size_t blocks = (ng + 255) / 256;
+        hipLaunchKernelGGL(k_fill_f32, dim3(unsigned(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, grad2d,
+                           ng);
+    }
+    if (views.items_total > 0 && g.n > 0) {
+#define VRS_BWD_W(w)                                                                    \
+    case w:                                                                             \
+        launch_render_bwd<w>(proj, uint32_t(g.n), gids, ranges, views, kn, grad2d, s); \
+        break;
+        switch (window) {
+            VRS_BWD_W(1) VRS_BWD_W(2) VRS_BWD_W(3) VRS_BWD_W(4) VRS_BWD_W(6) VRS_BWD_W(8) VRS_BWD_W(12)
+            VRS_BWD_W(16) VRS_BWD_W(24) VRS_BWD_W(32)
+            default: return VRS_ERR_UNSUPPORTED;
+        }
+#undef VRS_BWD_W
+    }
+    if (g.n > 0) {
+        hipLaunchKernelGGL(k_color_bwd, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, gv, grad2d, out);
+        hipLaunchKernelGGL(k_geom_bwd, dim3(unsigned((g.n + 127) / 128)), dim3(128), 0, s, g, gv, kn, grad2d, out);
+    }
+    return launch_status(hipGetLastError());
+}
+
+}  // namespace vrs

@@ -115,6 +115,32 @@ struct ItemViews {
     ItemView v[VRS_MAX_VIEWS];
 };
 
+// Plain views of a backward launch.  Block b belongs to the view v with
+// item_off[v] <= b < item_off[v + 1]; a 16x16 sort tile is one item, a
+// 32x32 tile four (its 16x16 subtiles, row-major).
+struct BwdView {
+    const float* rgba;  // forward output  [4][H][W]
+    const float* grad;  // dL/d(output)    [4][H][W]
+    int W, H, T, ntx;
+    uint32_t tile_off;
+    uint32_t item_off;
+};
+
+struct BwdViews {
+    int n;
+    uint32_t items_total;
+    BwdView v[VRS_MAX_VIEWS];
+};
+
+// Gradient outputs, the layouts of GaussPtrs.
+struct GradPtrs {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opac;
+    float* sh;
+};
+
 // Work items: view (5 bits) | class (2) | subtile (2) | sort-grid tile (23).
 __host__ __device__ inline uint32_t item_pack(int view, int cls, int sub, uint32_t tile) {
     return (uint32_t(view) << 27) | (uint32_t(cls) << 25) | (uint32_t(sub) << 23) | tile;

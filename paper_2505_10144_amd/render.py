@@ -107,6 +107,7 @@ class Renderer:
                _stream(self.stream))
         self.n_items = int(n_items.value)
         self.items_max = sizes.items_max
+        self.generation = 0  # forward passes run (the backward replays the latest)
 
     # -- sizes / buffers --------------------------------------------------------
     def _sizes(self, capacity):
@@ -202,7 +203,47 @@ class Renderer:
         self.preprocess(g)
         self.sort(g)
         self.blend()
+        self.generation += 1
         return self.images
+
+    def backward(self, g: Gaussians, grad_images: Sequence[torch.Tensor],
+                 images: Optional[Sequence[torch.Tensor]] = None) -> dict:
+        """Gradients of sum_v <grad_images[v], images[v]> with respect to the
+        Gaussian parameters, for the forward pass whose state (records,
+        sorted instances, ranges) this renderer currently holds.  ``images``
+        defaults to the renderer's own output buffers.  Plain views only."""
+        if g.n != self.n:
+            raise ValueError("Gaussian count differs from the renderer's")
+        images = list(images) if images is not None else self.images
+        if len(grad_images) != self.V or len(images) != self.V:
+            raise ValueError("one image and one gradient per view")
+        grads = [gi.contiguous().to(torch.float32) for gi in grad_images]
+        for gi, c in zip(grads, self.cams):
+            if tuple(gi.shape) != (4, c.height, c.width) or not gi.is_cuda:
+                raise ValueError("gradients must be (4, H, W) CUDA tensors")
+        imgs = [im.contiguous() for im in images]
+        need = int(L.load().vrs_backward_workspace_size(self.n, self.V))
+        if getattr(self, "bwd_ws", None) is None or self.bwd_ws.numel() < max(need, 256):
+            self.bwd_ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        dev = self.device
+        out = dict(means=torch.empty_like(g.means), log_scales=torch.empty_like(g.log_scales),
+                   quats=torch.empty_like(g.quats), opacity_logits=torch.empty_like(g.opacity_logits),
+                   sh=torch.zeros_like(g.sh))
+        gs = L.vrs_gaussian_grads()
+        gs.means = out["means"].data_ptr()
+        gs.log_scales = out["log_scales"].data_ptr()
+        gs.quats = out["quats"].data_ptr()
+        gs.opacity_logits = out["opacity_logits"].data_ptr()
+        gs.sh = out["sh"].data_ptr()
+        img_ptrs = (ctypes.c_void_p * self.V)(*[im.data_ptr() for im in imgs])
+        grad_ptrs = (ctypes.c_void_p * self.V)(*[gi.data_ptr() for gi in grads])
+        L.call("vrs_render_backward", ctypes.byref(g.struct()), _ptr(self.proj), _ptr(self.gids),
+               _ptr(self.ranges), self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), img_ptrs,
+               grad_ptrs, ctypes.byref(gs), _ptr(self.bwd_ws), ctypes.c_size_t(self.bwd_ws.numel()),
+               _ptr(self.status), _stream(self.stream))
+        # Keep the inputs alive until the kernels that read them are done.
+        self._bwd_keep = (imgs, grads)
+        return out
 
     def check(self):
         """Synchronise and raise if the device reported an error (capacity)."""

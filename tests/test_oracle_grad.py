@@ -107,3 +107,38 @@ def test_gradient_matches_central_differences(seed):
             assert rel < 2e-5, (name, k, fd, g.ravel()[k])
             checked[name] = checked.get(name, 0) + 1
     assert all(checked.get(n, 0) >= 3 for n, _ in fields), checked
+
+
+def test_vjp_matches_central_differences():
+    """The vector-Jacobian product (all four channels, so the alpha path is
+    covered too) against central differences of the NumPy forward pass."""
+    scene, cams = fd_scene(2)
+    params = synth.default_params(tile=16, window=8)
+    rng = np.random.default_rng(5)
+    Wt = [rng.standard_normal((4, c.height, c.width)) for c in cams]
+    grads, res, _ = ograd.vjp(scene, cams, params, Wt)
+    base_state = _state(res)
+
+    def functional(sc):
+        r = oracle.render(sc, cams, [synth.fovea_off()] * len(cams), params, oracle.OracleOptions(record=True))
+        return sum(float((w * im).sum()) for w, im in zip(Wt, r["images"])), r
+
+    checked = {}
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        arr = getattr(scene, name)
+        g = grads[name]
+        for k in np.argsort(-np.abs(g).ravel())[:4]:
+            h = 1e-7 * max(1.0, abs(arr.ravel()[k]))
+            vals, ok = [], True
+            for sgn in (1, -1):
+                a2 = arr.copy()
+                a2.ravel()[k] += sgn * h
+                val, r2 = functional(synth.Scene(**{**scene.__dict__, name: a2}))
+                ok = ok and _state(r2) == base_state
+                vals.append(val)
+            if not ok:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g.ravel()[k]) <= 2e-5 * max(abs(fd), 1e-9), (name, k, fd, g.ravel()[k])
+            checked[name] = checked.get(name, 0) + 1
+    assert all(checked.get(n, 0) >= 2 for n in ("means", "log_scales", "quats", "opacity_logits", "sh")), checked
