@@ -132,7 +132,8 @@ typedef struct {
     uint32_t items_max;      /* upper bound on render work items                   */
     size_t plan_bytes;       /* work list + per-view subtile class maps            */
     size_t sort_ws_bytes;    /* vrs_duplicate/vrs_sort workspace for `capacity`    */
-    size_t render_ws_bytes;  /* vrs_render_foveated workspace (pre-compose images) */
+    size_t render_ws_bytes;  /* vrs_render_foveated workspace: pre-compose images of
+                                foveated views, then the work-item ordering        */
 } vrs_sizes;
 
 /* Sizes of every buffer the other entry points need.  `capacity` is the
@@ -142,9 +143,9 @@ int vrs_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* fovea
                        int32_t n_views, const vrs_params* p, size_t capacity,
                        vrs_sizes* out);
 
-/* Foveation map (Sec. 4.3: "this mapping can be efficiently computed at the
- * start of each render pass and enables us to compute the exact number of
- * blocks to launch"; precomputed once per eye and reused).  Writes into
+/* Foveation map (Sec. 4.3: the tile-to-class mapping is cheap to build at
+ * the start of a frame and gives the exact block count of the single
+ * launch; it is built once per eye configuration and reused).  Writes into
  * `plan` (plan_bytes from vrs_workspace_size) the class of every 16x16
  * subtile of every view and a compact list of render work items: per
  * foveated view, one LOW item per periphery 32x32 tile and one HIGH/HYBRID
@@ -215,10 +216,14 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
  * LOW/HIGH/HYBRID items), followed by the periphery reconstruction of
  * foveated views (nearest-neighbour upsampling and a 3x3 binomial blur of
  * LOW pixels, Sec. 4.3).  proj/n: the records written by vrs_preprocess
- * for n Gaussians; gids/ranges: the sorted instances of vrs_sort.  rgba[v] is a device pointer to view v's output,
- * planar float [4][height][width] (R, G, B, alpha = 1 - T).  `plan` and
- * n_items come from vrs_fovea_plan for the same cameras/foveas/params;
- * `ws` must hold render_ws_bytes. */
+ * for n Gaussians; gids/ranges: the sorted instances of vrs_sort.  rgba[v]
+ * is a device pointer to view v's output, planar float [4][height][width]
+ * (R, G, B, alpha = 1 - T).  `plan` and n_items come from vrs_fovea_plan for
+ * the same cameras/foveas/params; `ws` (256-byte aligned) must hold
+ * render_ws_bytes.  The work items run longest first: before the blend, one
+ * radix pass orders them by the length of their tile's list on a log scale
+ * (equal keys keep plan order), which changes the scheduling only, never
+ * the output. */
 int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
                         const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
                         const vrs_params* p, const void* plan, uint32_t n_items,

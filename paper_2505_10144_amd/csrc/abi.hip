@@ -27,6 +27,10 @@ int launch_blend(const float*, uint32_t, const uint32_t*, const uint32_t*, const
                  const RenderViews&, const Knobs&, int, unsigned long long*, hipStream_t);
 int launch_compose(const RenderViews&, const uint8_t*, hipStream_t);
 bool window_supported(int w);
+size_t order_ws_bytes(size_t items_max);
+const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, const uint32_t* count_dev,
+                                   size_t items_max, const uint32_t* ranges, const RenderViews& views, void* ws,
+                                   hipStream_t s);
 
 int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, void* plan, size_t items_max, hipStream_t s);
 }  // namespace vrs
@@ -52,7 +56,9 @@ struct Layout {
     uint32_t items_max;
     size_t cls_bytes;
     size_t plan_bytes;
-    size_t render_ws_floats;
+    size_t render_ws_floats;  // pre-compose images of foveated views
+    size_t order_off;         // bytes: the work-item ordering area after them
+    size_t render_ws_bytes;
 };
 
 bool finite_f(float x) { return isfinite(x); }
@@ -115,6 +121,8 @@ int make_layout(const vrs_camera* cams, const vrs_fovea* foveas, int n_views, co
     L.cls_bytes = size_t(cls);
     L.plan_bytes = kPlanItemsOff + size_t(items) * 4 + ((size_t(cls) + 255) & ~size_t(255));
     L.render_ws_floats = size_t(pre);
+    L.order_off = ((size_t(pre) * sizeof(float)) + 255) & ~size_t(255);
+    L.render_ws_bytes = L.order_off + order_ws_bytes(size_t(items));
     return VRS_OK;
 }
 
@@ -213,7 +221,7 @@ int vrs_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* fovea
     out->plan_bytes = L.plan_bytes;
     const size_t a = dup_ws_bytes(nv), b = sort_ws_bytes(capacity);
     out->sort_ws_bytes = a > b ? a : b;
-    out->render_ws_bytes = L.render_ws_floats * sizeof(float);
+    out->render_ws_bytes = L.render_ws_bytes;
     return VRS_OK;
 }
 
@@ -359,6 +367,7 @@ int render_setup(int32_t n, const void* proj, const uint32_t* gids, const uint32
     if (n_items > 0 && (!proj || !gids || !ranges || !aligned(proj, 16))) return VRS_ERR_INVALID_ARG;
     if (L.render_ws_floats > 0 && (!ws || ws_bytes < L.render_ws_floats * sizeof(float)))
         return VRS_ERR_INVALID_ARG;
+    if (n_items > 0 && (!ws || ws_bytes < L.render_ws_bytes || !aligned(ws, 256))) return VRS_ERR_INVALID_ARG;
     memset(&R, 0, sizeof(R));
     R.n = n_views;
     for (int v = 0; v < n_views; ++v) {
@@ -411,8 +420,13 @@ int vrs_blend(const void* proj, int32_t n, const uint32_t* gids, const uint32_t*
     Layout L;
     int rc = render_setup(n, proj, gids, ranges, cams, foveas, n_views, p, plan, n_items, rgba, ws, ws_bytes, R, L);
     if (rc != VRS_OK) return rc;
-    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, plan_items(plan), n_items, R,
-                        knobs(p), p->window, nullptr, reinterpret_cast<hipStream_t>(stream));
+    if (n_items == 0) return VRS_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint32_t* items = launch_order_items(plan_items(plan), n_items, static_cast<const uint32_t*>(plan),
+                                               L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off, s);
+    if (!items) return VRS_ERR_HIP;
+    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items, R, knobs(p),
+                        p->window, nullptr, s);
 }
 
 int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
@@ -424,9 +438,13 @@ int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uin
     if (!counters_dev) return VRS_ERR_INVALID_ARG;
     int rc = render_setup(n, proj, gids, ranges, cams, foveas, n_views, p, plan, n_items, rgba, ws, ws_bytes, R, L);
     if (rc != VRS_OK) return rc;
-    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, plan_items(plan), n_items, R,
-                        knobs(p), p->window, reinterpret_cast<unsigned long long*>(counters_dev),
-                        reinterpret_cast<hipStream_t>(stream));
+    if (n_items == 0) return VRS_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint32_t* items = launch_order_items(plan_items(plan), n_items, static_cast<const uint32_t*>(plan),
+                                               L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off, s);
+    if (!items) return VRS_ERR_HIP;
+    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items, R, knobs(p),
+                        p->window, reinterpret_cast<unsigned long long*>(counters_dev), s);
 }
 
 int vrs_compose(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,

@@ -24,6 +24,9 @@
 
 namespace vrs {
 
+size_t sort_ws_bytes(size_t capacity);
+int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, hipStream_t);
+
 constexpr int kRenderThreads = 256;
 constexpr int kBatch = 64;      // entries staged per wave and batch
 constexpr int kStage = 7;       // float4 per staged entry
@@ -360,6 +363,50 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
     }
 #undef VRS_W
     return launch_status(hipGetLastError());
+}
+
+// Longest-first order of the work items (list scheduling: the blocks that
+// take longest start first, so they do not extend the end of the launch).
+// The cost of an item is the length of its sort tile's list; the key is
+// that length on a log scale with 16 steps per octave, descending, so one
+// 8-bit radix pass orders the items (stably: equal keys keep plan order).
+__global__ void __launch_bounds__(256) k_item_keys(const uint32_t* __restrict__ items, uint32_t n,
+                                                   const uint32_t* __restrict__ ranges, RenderViews views,
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t it = items[i];
+    const RenderView& V = views.v[item_view(it)];
+    const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + item_tile(it)];
+    const uint32_t c = rg.y - rg.x;
+    uint32_t b = 0;
+    if (c != 0) {
+        const int e = 31 - __clz(int(c));
+        const uint32_t m = e >= 4 ? (c >> (e - 4)) & 15u : (c << (4 - e)) & 15u;
+        b = min(255u, uint32_t(e) * 16u + m + 1u);
+    }
+    keys[i] = uint64_t(255u - b);
+    vals[i] = it;
+}
+
+size_t order_ws_bytes(size_t items_max) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    return al(items_max * 8) + al(items_max * 4) + al(sort_ws_bytes(items_max));
+}
+
+// Writes the ordered items to the second region of `ws` and returns them.
+const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, const uint32_t* count_dev,
+                                   size_t items_max, const uint32_t* ranges, const RenderViews& views, void* ws,
+                                   hipStream_t s) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    char* base = static_cast<char*>(ws);
+    uint64_t* keys = reinterpret_cast<uint64_t*>(base);
+    uint32_t* vals = reinterpret_cast<uint32_t*>(base + al(items_max * 8));
+    void* sws = base + al(items_max * 8) + al(items_max * 4);
+    hipLaunchKernelGGL(k_item_keys, dim3((n_items + 255) / 256), dim3(256), 0, s, items, n_items, ranges, views,
+                       keys, vals);
+    if (launch_sort_pairs(keys, vals, count_dev, n_items, 8, sws, s) != VRS_OK) return nullptr;
+    return vals;
 }
 
 int launch_compose(const RenderViews& views, const uint8_t* cls, hipStream_t s) {
