@@ -45,9 +45,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--window", type=int, default=16)
+    ap.add_argument("--schedule", type=int, default=0, help="blend schedule: 0 one block per item, 1 persistent")
+    ap.add_argument("--blend-batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd leg")
     ap.add_argument("--diff-steps", type=int, default=10)
+    ap.add_argument("--diff-only", action="store_true", help="run only the fwd+bwd leg (for profiling)")
     ap.add_argument("--cpu-tiles", type=int, default=24, help="32x32 tiles per eye in the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -185,7 +188,11 @@ def main():
     from paper_2505_10144_amd.render import Renderer, upload
 
     torch.cuda.set_device(0)
+    if args.diff_only:
+        print(json.dumps({"fwd_bwd": diff_leg(args.diff_steps, 3)}), flush=True)
+        return
     scene, cams, fovs, params = synth.config_stereo(0, n=args.n, window=args.window)
+    params = params.replace(schedule=args.schedule, blend_batch=args.blend_batch)
     r = Renderer(cams, fovs, params, scene.n)
     g = upload(scene)
     n_cand = r.ensure_capacity(g)
@@ -244,7 +251,8 @@ def main():
         "config": {"workload": "vr-stereo-foveated: 500k cluster+slab Gaussians, 2 eyes 2064x2208, "
                                "110 deg FoV, 64 mm baseline, 15 deg fovea, 10% band, W=16",
                    "n_gaussians": scene.n, "views": 2, "width": 2064, "height": 2208,
-                   "fovea_deg": 15.0, "window": args.window, "sort_tile": 32},
+                   "fovea_deg": 15.0, "window": args.window, "sort_tile": 32,
+                   "schedule": args.schedule, "blend_batch": args.blend_batch},
         "roofline": {"bound": "alu", "kernel": kernel_key, "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (FP32 VALU lane-ops)",
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic},

@@ -102,10 +102,16 @@ typedef struct {
     float band_frac;
 } vrs_fovea;
 
-/* Renderer knobs.  tile: 16 (plain views) -- foveated views always use 32x32
- * sort tiles split into 16x16 subtiles; window: per-sample resort window
- * length W, 1..32 (Sec. 4.1); blend_batch: list entries staged per wave and
- * batch, 64 (performance only, never changes the output).
+/* Blend schedules (performance only; the output is identical). */
+#define VRS_SCHEDULE_ONESHOT 0    /* one block per work item, longest first        */
+#define VRS_SCHEDULE_PERSISTENT 1 /* a chip-filling grid whose waves draw (item,    \
+                                     row) units longest first from an atomic counter */
+
+/* Renderer knobs.  tile: 16 or 32 for plain views (a 32x32 tile is rendered
+ * as four 16x16 subtiles) -- foveated views always use 32x32 sort tiles;
+ * window: per-sample resort window length W, 1..32 (Sec. 4.1); blend_batch:
+ * list entries staged per wave and batch, 16, 32 or 64, and schedule, one
+ * of VRS_SCHEDULE_* (both performance only, never changing the output).
  * z_near: near cull on camera z; alpha_min: culling and skip threshold
  * (1/255, Sec. 4.2); alpha_max: alpha clamp (0.99); t_min: transmittance at
  * which a sample stops (1e-4); dilation: px^2 added to the 2D covariance
@@ -114,6 +120,7 @@ typedef struct {
     int32_t tile;
     int32_t window;
     int32_t blend_batch;
+    int32_t schedule;
     float z_near;
     float alpha_min;
     float alpha_max;

@@ -17,6 +17,7 @@ VRS_MAX_VIEWS = 32
 VRS_MAX_WINDOW = 32
 VRS_RECORD_FLOATS = 32
 VRS_CLASS_LOW, VRS_CLASS_HIGH, VRS_CLASS_HYBRID, VRS_CLASS_PLAIN = 0, 1, 2, 3
+VRS_SCHEDULE_ONESHOT, VRS_SCHEDULE_PERSISTENT = 0, 1
 PLAN_ITEMS_OFFSET = 256
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -45,7 +46,7 @@ class vrs_fovea(ctypes.Structure):
 
 class vrs_params(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("window", ctypes.c_int32),
-                ("blend_batch", ctypes.c_int32), ("z_near", ctypes.c_float),
+                ("blend_batch", ctypes.c_int32), ("schedule", ctypes.c_int32), ("z_near", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("background", ctypes.c_float * 3)]
@@ -177,6 +178,7 @@ def make_params(p) -> vrs_params:
     o.tile = int(p.tile)
     o.window = int(p.window)
     o.blend_batch = int(p.blend_batch) if p.blend_batch else 64
+    o.schedule = int(getattr(p, "schedule", VRS_SCHEDULE_ONESHOT))
     o.z_near = float(p.z_near)
     o.alpha_min = float(p.alpha_min)
     o.alpha_max = float(p.alpha_max)

@@ -23,8 +23,9 @@ int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*,
 constexpr size_t kProjBytesPerSlot = kRec * sizeof(float) + 224;
 size_t dup_ws_bytes(size_t nslots) { return (nslots + scan_tmp_words(nslots) + 64) * sizeof(uint32_t); }
 int launch_tile_ranges(const uint64_t*, const uint32_t*, size_t, uint32_t, uint32_t*, hipStream_t);
-int launch_blend(const float*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, uint32_t,
-                 const RenderViews&, const Knobs&, int, unsigned long long*, hipStream_t);
+int launch_blend(const float*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*, int,
+                 int, const RenderViews&, const Knobs&, int, unsigned long long*, hipStream_t);
+uint32_t* order_counter(void* ws);
 int launch_compose(const RenderViews&, const uint8_t*, hipStream_t);
 bool window_supported(int w);
 size_t order_ws_bytes(size_t items_max);
@@ -68,7 +69,8 @@ int check_params(const vrs_params* p) {
     if (p->tile != 16 && p->tile != 32) return VRS_ERR_INVALID_ARG;
     if (p->window < 1 || p->window > VRS_MAX_WINDOW) return VRS_ERR_INVALID_ARG;
     if (!window_supported(p->window)) return VRS_ERR_UNSUPPORTED;
-    if (p->blend_batch != 64) return VRS_ERR_UNSUPPORTED;
+    if (p->blend_batch != 16 && p->blend_batch != 32 && p->blend_batch != 64) return VRS_ERR_UNSUPPORTED;
+    if (p->schedule != VRS_SCHEDULE_ONESHOT && p->schedule != VRS_SCHEDULE_PERSISTENT) return VRS_ERR_INVALID_ARG;
     if (!(p->z_near > 0.f) || !finite_f(p->z_near)) return VRS_ERR_INVALID_ARG;
     if (!(p->alpha_min > 0.f && p->alpha_min < 1.f)) return VRS_ERR_INVALID_ARG;
     if (!(p->alpha_max >= p->alpha_min && p->alpha_max <= 1.f)) return VRS_ERR_INVALID_ARG;
@@ -425,7 +427,8 @@ int vrs_blend(const void* proj, int32_t n, const uint32_t* gids, const uint32_t*
     const uint32_t* items = launch_order_items(plan_items(plan), n_items, static_cast<const uint32_t*>(plan),
                                                L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off, s);
     if (!items) return VRS_ERR_HIP;
-    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items, R, knobs(p),
+    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items,
+                        order_counter(static_cast<char*>(ws) + L.order_off), p->blend_batch, p->schedule, R, knobs(p),
                         p->window, nullptr, s);
 }
 
@@ -443,7 +446,8 @@ int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uin
     const uint32_t* items = launch_order_items(plan_items(plan), n_items, static_cast<const uint32_t*>(plan),
                                                L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off, s);
     if (!items) return VRS_ERR_HIP;
-    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items, R, knobs(p),
+    return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items,
+                        order_counter(static_cast<char*>(ws) + L.order_off), p->blend_batch, p->schedule, R, knobs(p),
                         p->window, reinterpret_cast<unsigned long long*>(counters_dev), s);
 }
 

@@ -26,6 +26,7 @@ namespace vrs {
 
 size_t sort_ws_bytes(size_t capacity);
 int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, hipStream_t);
+int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 
 constexpr int kRenderThreads = 256;
 constexpr int kBatch = 64;      // entries staged per wave and batch
@@ -114,18 +115,17 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// STATS = true is the instrumented variant: it also counts, per launch,
-// evaluated (sample, entry) pairs, pairs that reach alpha_min, in-image
-// samples, samples stopped by t_min and list entries staged.
+// One wave's share of a work item: rows 4 wv .. 4 wv + 3 of a 16x16 (sub)tile,
+// or rows 8 wv .. 8 wv + 7 of a LOW tile's half-resolution samples.  `st` is
+// the wave's own LDS slice; `batch` (<= kBatch) list entries are staged at a
+// time.  STATS = true is the instrumented variant: it also counts evaluated
+// (sample, entry) pairs, pairs that reach alpha_min, in-image samples,
+// samples stopped by t_min and list entries staged.
 template <int W, bool STATS>
-__global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restrict__ proj, uint32_t n_gauss,
-                                                           const uint32_t* __restrict__ gids,
-                                                           const uint32_t* __restrict__ ranges,
-                                                           const uint32_t* __restrict__ items,
-                                                           RenderViews views, Knobs kn,
-                                                           unsigned long long* __restrict__ stats) {
-    __shared__ float4 stage[kRenderThreads / 64][kBatch][kStage];
-    const uint32_t item = items[blockIdx.x];
+__device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], const float* __restrict__ proj,
+                                   uint32_t n_gauss, const uint32_t* __restrict__ gids,
+                                   const uint32_t* __restrict__ ranges, const RenderViews& views, const Knobs& kn,
+                                   int batch, unsigned long long* __restrict__ stats) {
     const int v = item_view(item);
     const int cls = item_class(item);
     const int sub = item_sub(item);
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
     const int T = V.foveated ? 32 : V.T;
     const int tx = int(tile % uint32_t(V.ntx)), ty = int(tile / uint32_t(V.ntx));
     const int ox = tx * T, oy = ty * T;  // sort-tile origin (pixels)
-    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const int lane = int(threadIdx.x) & 63, t = wv * 64 + lane;
 
     // Sample of this thread, relative to the tile origin.
     int px, py;      // first pixel covered
@@ -165,7 +165,6 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
 
     const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
-    float4(*st)[kStage] = stage[wv];
     const float amax = kn.alpha_max, tmin = kn.t_min;
     uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0;
 
@@ -183,9 +182,9 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
         ry0 = float(oy + by + 4 * wv) + 0.5f; ry1 = float(oy + by + 4 * wv) + 3.5f;
     }
 
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBatch) {
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += uint32_t(batch)) {
         if (__ballot(acc.alive) == 0ull) break;
-        const int nb = int(min(uint32_t(kBatch), rg.y - b0));
+        const int nb = int(min(uint32_t(batch), rg.y - b0));
         bool rel = false;
         if (lane < nb) {
             const uint32_t gid = gids[b0 + lane];
@@ -301,6 +300,38 @@ __global__ void __launch_bounds__(kRenderThreads) k_render(const float* __restri
     }
 }
 
+// K6 launch.  One-shot schedule (PERSIST = false): one block per work item,
+// in the given (longest-first) order.  Persistent schedule: a grid that
+// fills the chip once, whose waves take (item, wave row) units in order from
+// an atomic counter until none are left, so a wave that finishes early
+// starts new work at once instead of idling until its block's slowest wave
+// ends.  The counter must be zero at launch; every wave exits after drawing
+// a unit past the end.
+template <int W, bool STATS, bool PERSIST>
+__global__ void __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(W <= 16 ? 2 : 1)))
+k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __restrict__ gids,
+         const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ items, uint32_t n_items,
+         uint32_t* __restrict__ counter, int batch, RenderViews views, Knobs kn,
+         unsigned long long* __restrict__ stats) {
+    __shared__ float4 stage[kRenderThreads / 64][kBatch][kStage];
+    const int slot = int(threadIdx.x) >> 6;
+    if (!PERSIST) {
+        render_unit<W, STATS>(items[blockIdx.x], slot, stage[slot], proj, n_gauss, gids, ranges, views, kn, batch,
+                              stats);
+        return;
+    }
+    const int lane = int(threadIdx.x) & 63;
+    const uint32_t n_units = 4u * n_items;
+    for (;;) {
+        uint32_t u = 0;
+        if (lane == 0) u = atomicAdd(counter, 1u);
+        u = __shfl(u, 0);
+        if (u >= n_units) break;
+        render_unit<W, STATS>(items[u >> 2], int(u & 3u), stage[slot], proj, n_gauss, gids, ranges, views, kn, batch,
+                              stats);
+    }
+}
+
 // K7: LOW pixels of a foveated view take the 3x3 binomial blur of the
 // nearest-neighbour-upsampled image (coordinates clamped to the image); other
 // pixels are copied.
@@ -332,16 +363,44 @@ __global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __
     }
 }
 
+// Blocks of a persistent launch: enough to fill every CU at the kernel's
+// occupancy, never more than the work items.
+template <typename K>
+static uint32_t persistent_blocks(K kernel, uint32_t n_items) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kRenderThreads, 0) != hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+        return n_items;
+    const uint64_t b = uint64_t(cus) * uint64_t(per_cu);
+    return uint32_t(b < n_items ? b : n_items);
+}
+
+template <int W, bool STATS>
+static void launch_render_ws(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
+                             const uint32_t* items, uint32_t n_items, uint32_t* counter, int batch, int schedule,
+                             const RenderViews& views, const Knobs& kn, unsigned long long* stats, hipStream_t s) {
+    if (schedule == VRS_SCHEDULE_PERSISTENT) {
+        const uint32_t blocks = persistent_blocks(k_render<W, STATS, true>, n_items);
+        hipLaunchKernelGGL((k_render<W, STATS, true>), dim3(blocks), dim3(kRenderThreads), 0, s, proj, n_gauss, gids,
+                           ranges, items, n_items, counter, batch, views, kn, stats);
+    } else {
+        hipLaunchKernelGGL((k_render<W, STATS, false>), dim3(n_items), dim3(kRenderThreads), 0, s, proj, n_gauss,
+                           gids, ranges, items, n_items, counter, batch, views, kn, stats);
+    }
+}
+
 template <int W>
 static void launch_render_w(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
-                            const uint32_t* items, uint32_t n_items, const RenderViews& views, const Knobs& kn,
-                            unsigned long long* stats, hipStream_t s) {
+                            const uint32_t* items, uint32_t n_items, uint32_t* counter, int batch, int schedule,
+                            const RenderViews& views, const Knobs& kn, unsigned long long* stats, hipStream_t s) {
     if (stats)
-        hipLaunchKernelGGL((k_render<W, true>), dim3(n_items), dim3(kRenderThreads), 0, s, proj, n_gauss, gids,
-                           ranges, items, views, kn, stats);
+        launch_render_ws<W, true>(proj, n_gauss, gids, ranges, items, n_items, counter, batch, schedule, views, kn,
+                                  stats, s);
     else
-        hipLaunchKernelGGL((k_render<W, false>), dim3(n_items), dim3(kRenderThreads), 0, s, proj, n_gauss, gids,
-                           ranges, items, views, kn, stats);
+        launch_render_ws<W, false>(proj, n_gauss, gids, ranges, items, n_items, counter, batch, schedule, views, kn,
+                                   stats, s);
 }
 
 bool window_supported(int w) {
@@ -352,11 +411,18 @@ bool window_supported(int w) {
 }
 
 int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
-                 const uint32_t* items, uint32_t n_items, const RenderViews& views, const Knobs& kn, int window,
-                 unsigned long long* stats, hipStream_t s) {
+                 const uint32_t* items, uint32_t n_items, uint32_t* counter, int batch, int schedule,
+                 const RenderViews& views, const Knobs& kn, int window, unsigned long long* stats, hipStream_t s) {
     if (n_items == 0) return VRS_OK;
-#define VRS_W(w) \
-    case w: launch_render_w<w>(proj, n_gauss, gids, ranges, items, n_items, views, kn, stats, s); break;
+    if (schedule == VRS_SCHEDULE_PERSISTENT) {
+        const int rc = launch_fill_u32(counter, 1, 0u, s);
+        if (rc != VRS_OK) return rc;
+    }
+#define VRS_W(w)                                                                                                  \
+    case w:                                                                                                       \
+        launch_render_w<w>(proj, n_gauss, gids, ranges, items, n_items, counter, batch, schedule, views, kn, stats, \
+                           s);                                                                                    \
+        break;
     switch (window) {
         VRS_W(1) VRS_W(2) VRS_W(3) VRS_W(4) VRS_W(6) VRS_W(8) VRS_W(12) VRS_W(16) VRS_W(24) VRS_W(32)
         default: return VRS_ERR_UNSUPPORTED;
@@ -389,17 +455,21 @@ __global__ void __launch_bounds__(256) k_item_keys(const uint32_t* __restrict__ 
     vals[i] = it;
 }
 
+// Ordering area: [0, 256) the persistent schedule's unit counter, then the
+// keys, the ordered items and the radix-sort scratch.
 size_t order_ws_bytes(size_t items_max) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    return al(items_max * 8) + al(items_max * 4) + al(sort_ws_bytes(items_max));
+    return 256 + al(items_max * 8) + al(items_max * 4) + al(sort_ws_bytes(items_max));
 }
 
-// Writes the ordered items to the second region of `ws` and returns them.
+uint32_t* order_counter(void* ws) { return static_cast<uint32_t*>(ws); }
+
+// Writes the ordered items into the ordering area `ws` and returns them.
 const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, const uint32_t* count_dev,
                                    size_t items_max, const uint32_t* ranges, const RenderViews& views, void* ws,
                                    hipStream_t s) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    char* base = static_cast<char*>(ws);
+    char* base = static_cast<char*>(ws) + 256;
     uint64_t* keys = reinterpret_cast<uint64_t*>(base);
     uint32_t* vals = reinterpret_cast<uint32_t*>(base + al(items_max * 8));
     void* sws = base + al(items_max * 8) + al(items_max * 4);

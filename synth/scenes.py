@@ -34,11 +34,14 @@ def _f32(x):
 class Params:
     """Renderer knobs.  ``tile`` is 16 (plain) or 32 (foveated, split into 16^2
     subtiles near the fovea); ``window`` is the per-sample resort window length;
-    ``blend_batch`` is the number of list entries staged per block batch (a
-    performance knob that never changes the output)."""
+    ``blend_batch`` is the number of list entries staged per wave and batch
+    and ``schedule`` selects the blend launch (0 one block per work item,
+    1 persistent waves); both are performance knobs that never change the
+    output."""
     tile: int = 16
     window: int = 16
     blend_batch: int = 64
+    schedule: int = 0
     z_near: float = float(F32(0.2))
     alpha_min: float = float(F32(1.0 / 255.0))
     alpha_max: float = float(F32(0.99))

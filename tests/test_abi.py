@@ -69,6 +69,7 @@ def test_workspace_size_plain_and_tile32():
 
 @pytest.mark.parametrize("bad", [
     dict(tile=8), dict(window=0), dict(window=33), dict(alpha_min=0.0), dict(alpha_min=1.0),
+    dict(schedule=2), dict(schedule=-1),
     dict(t_min=0.0), dict(z_near=0.0), dict(dilation=-1.0), dict(alpha_max=0.001),
 ])
 def test_invalid_params_rejected(bad):

@@ -148,6 +148,26 @@ def test_background_colour(R):
     compare(imgs, ref)
 
 
+def test_schedules_and_batches_are_bit_identical(R):
+    """The blend schedule and the staging batch are performance knobs: every
+    combination gives the same bits as one block per item with 64-entry
+    batches, on mixed plain and foveated views."""
+    scene = synth.cluster_scene(5, 20000, log_scale=(-4.5, 0.6))
+    rng = np.random.default_rng(9)
+    cams = synth.ring_cameras(rng, 3, 3.0, [(200, 150), (96, 130), (160, 160)])
+    fovs = [synth.fovea_off(), synth.fovea_at_center(cams[1], 12.0), synth.fovea_off()]
+    ref = None
+    for schedule in (0, 1):
+        for batch in (64, 32, 16):
+            params = synth.default_params(tile=16, window=8, blend_batch=batch, schedule=schedule)
+            _, _, imgs = run_gpu(R, scene, cams, fovs, params)
+            if ref is None:
+                ref = imgs
+                continue
+            for a, b in zip(imgs, ref):
+                assert np.array_equal(a, b), (schedule, batch)
+
+
 def test_deterministic_repeat(R):
     scene, cams, fovs, params = synth.config_stereo(2, n=20000, width=320, height=288)
     r, g, a = run_gpu(R, scene, cams, fovs, params)
