@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-diff", action="store_true", help="skip the fwd+bwd leg")
     ap.add_argument("--diff-steps", type=int, default=10)
     ap.add_argument("--diff-only", action="store_true", help="run only the fwd+bwd leg (for profiling)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-view leg")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched multi-view leg")
     ap.add_argument("--cpu-tiles", type=int, default=24, help="32x32 tiles per eye in the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -173,6 +175,46 @@ def diff_leg(steps, warmup):
             "n_gaussians": scene.n, "views": V}
 
 
+def batch_leg(steps, log=None):
+    """The batched multi-view form: 1M cluster Gaussians rendered to 16 views
+    of mixed size (4 each of 512^2, 1024^2, 1920x1080, 2064x2208) and FoV, a
+    random half foveated, in one call sequence (one preprocess, one sort, one
+    blend launch over all views).  The renderer knobs come from the autotuner
+    (cached per configuration in a JSON file); the same knobs are then timed
+    as 16 separate single-view renders for comparison."""
+    import tempfile
+    import torch
+    import synth
+    from paper_2505_10144_amd.render import Renderer, upload
+    from paper_2505_10144_amd.tune import time_frames, tune
+    scene, cams, fovs, params = synth.config_batch(0)
+    g = upload(scene)
+    cache = os.environ.get("VRS_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "vrs_tune_cache.json"))
+    t0 = time.perf_counter()
+    res = tune(g, cams, fovs, params, cache_path=cache, steps=3, log=log)
+    t_tune = time.perf_counter() - t0
+    p = res.params
+    r = Renderer(cams, fovs, p, scene.n)
+    r.ensure_capacity(g)
+    batched = time_frames(r, g, steps)
+    n_items = r.n_items
+    del r
+    torch.cuda.empty_cache()
+    sep = 0.0
+    for c, f in zip(cams, fovs):
+        r1 = Renderer([c], [f], p, scene.n)
+        r1.ensure_capacity(g)
+        sep += time_frames(r1, g, steps)
+        del r1
+    torch.cuda.empty_cache()
+    return {"batched_ms": round(batched, 4), "separate_ms": round(sep, 4),
+            "speedup": round(sep / batched, 3), "views": len(cams), "items": n_items,
+            "tuned": {k: getattr(p, k) for k in ("tile", "window", "blend_batch", "schedule")},
+            "tune_s": round(t_tune, 1), "tune_cached": res.cached,
+            "workload": "batch: 1M cluster Gaussians, 16 views (4 each 512^2, 1024^2, 1920x1080, 2064x2208), "
+                        "FoV U[60,120] deg, 8 foveated (15 deg)"}
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -190,6 +232,10 @@ def main():
     torch.cuda.set_device(0)
     if args.diff_only:
         print(json.dumps({"fwd_bwd": diff_leg(args.diff_steps, 3)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": batch_leg(5, log=lambda row: print(row, file=sys.stderr, flush=True))}),
+              flush=True)
         return
     scene, cams, fovs, params = synth.config_stereo(0, n=args.n, window=args.window)
     params = params.replace(schedule=args.schedule, blend_batch=args.blend_batch)
@@ -259,12 +305,17 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "work": dict(work, candidates=n_cand, instances=n_kept, items=r.n_items),
     }
+    n_items = r.n_items
+    del r, g
+    torch.cuda.empty_cache()
     if not args.no_diff:
-        del r, g
-        torch.cuda.empty_cache()
         out["fwd_bwd"] = diff_leg(args.diff_steps, 3)
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batch"] = batch_leg(5)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, cams, fovs, params, r.n_items, args.cpu_tiles)
+        out["cpu_baseline"] = cpu_baseline(scene, cams, fovs, params, n_items, args.cpu_tiles)
     print(json.dumps(out), flush=True)
 
 

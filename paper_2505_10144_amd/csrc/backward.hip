@@ -16,19 +16,28 @@
 // then chains dL/dalpha through alpha = opacity 2^(-|z|^2 / h^2) to the 12
 // per-view splat parameters of the render record (M, a3, mean image point,
 // opacity, RGB).  The window holds (depth, alpha, arrival index).  The
-// records of the last four staged batches stay in a block-shared LDS ring
+// records of the last three staged batches stay in a block-shared LDS ring
 // beside their gradient accumulators; a batch's sums go to the per-view
 // [Gaussian][12] buffer with one global atomic per value when the batch
 // leaves the ring.  A window entry emitted after its batch left the ring is
-// re-read from HBM and accumulated with global atomics.  When every emitting
-// lane of a wave emits the same entry (the common case), the wave sums the
-// 12 values first and one lane adds them.
+// re-read from HBM and accumulated with global atomics.
+//
+// The LDS accumulators are 64-bit fixed point, added with integer atomics:
+// on gfx950, LDS float atomics run far below the rate of LDS integer
+// atomics, and the lanes of a wave mostly emit different entries (their
+// windows differ), so the adds cannot be combined across lanes first.  Each
+// (entry, value) accumulator takes its binary scale from its first nonzero
+// contribution g0: units of 2^(e0 + 20 - 54) with |g0| < 2^e0, so
+// contributions up to 2^20 |g0| are exact to 2^-34 |g0| and 256 of them
+// cannot overflow.  A larger contribution bypasses the accumulator and is
+// added to the global buffer directly (float atomic).
 //
 // K8b (k_color_bwd, k_geom_bwd) chains the per-view splat gradients to the
 // raw parameters (means, log-scales, quaternions, opacity logits, SH), one
-// thread per Gaussian: the set-up geometry of K1 and the SH colour are
-// re-evaluated in FP64 forward-mode dual numbers, one pass per parameter
-// they depend on, which gives exact derivatives of the formulas K1 uses.
+// thread per Gaussian.  The set-up geometry of K1 is re-evaluated in FP64
+// forward-mode dual numbers, one pass per geometric parameter, which gives
+// exact derivatives of the formulas K1 uses; the SH colour is differentiated
+// with the basis polynomials' analytic gradients.
 #include <float.h>
 
 #include "geom.h"
@@ -37,10 +46,12 @@ namespace vrs {
 
 constexpr int kBwdThreads = 256;
 constexpr int kBwdBatch = 64;  // entries staged per batch (one per lane of a wave)
-constexpr int kRingBatches = 4;
+constexpr int kRingBatches = 3;
 constexpr int kRing = kBwdBatch * kRingBatches;
 constexpr int kG = 12;  // gradient values per (view, Gaussian)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kUnset = -0x7FFFFFFF;   // accumulator scale not chosen yet
+constexpr int kHead = 20;             // headroom bits over the first contribution
 
 // Gradient slots of one (view, Gaussian).
 enum GradField : int {
@@ -99,10 +110,28 @@ struct BWindow {
     }
 };
 
-__device__ inline float wave_sum(float x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-    return x;
+// Fixed-point accumulation of one contribution (see above).  Returns false
+// when it does not fit the accumulator's range; the caller adds it elsewhere.
+__device__ inline bool fixed_add(unsigned long long* acc, int* scale, float g) {
+    int e = *scale;
+    if (e == kUnset) {
+        int fe;
+        frexpf(g, &fe);  // |g| < 2^fe
+        const int want = fe + kHead;
+        const int old = atomicCAS(scale, kUnset, want);
+        e = old == kUnset ? want : old;
+    }
+    const float x = ldexpf(g, 30 - e);  // exact power-of-two scaling
+    if (!(fabsf(x) < 1073741824.f)) return false;
+    const int hi = int(x);  // x - hi is exact, and so is its product with 2^24
+    const int lo = __float2int_rn((x - float(hi)) * 16777216.f);
+    const long long v = (static_cast<long long>(hi) << 24) + lo;
+    atomicAdd(acc, static_cast<unsigned long long>(v));
+    return true;
+}
+
+__device__ inline float fixed_value(unsigned long long acc, int scale) {
+    return float(ldexp(double(static_cast<long long>(acc)), scale - 54));
 }
 
 // Staged form of one list entry (7 float4, as in k_render): tile-relative
@@ -126,7 +155,8 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
                                                             Knobs kn, float* __restrict__ grad2d) {
     __shared__ float4 ring[kRing][7];
     __shared__ float4 ring_box[kRing];
-    __shared__ float acc[kRing][kG];
+    __shared__ unsigned long long acc[kRing][kG];
+    __shared__ int acc_scale[kRing][kG];
     __shared__ uint32_t ring_gid[kRing];
 
     const uint32_t item = blockIdx.x;
@@ -248,28 +278,12 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             C2 = n2;
             Tc = Tn;
         }
-        const int l0 = __builtin_ctzll(vm);
-        const uint32_t k0 = __shfl(ek, l0);
-        if (__ballot(valid && ek != k0) == 0ull) {
-            // One entry for the whole wave: reduce, then one lane adds.
+        if (valid) {
+            float* dst = vgrad + size_t(gid) * kG;
 #pragma unroll
-            for (int k = 0; k < kG; ++k) g[k] = wave_sum(g[k]);
-            if (lane == l0) {
-                if (in_ring) {
-#pragma unroll
-                    for (int k = 0; k < kG; ++k) atomicAdd(&acc[sl][k], g[k]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < kG; ++k) unsafeAtomicAdd(&vgrad[size_t(gid) * kG + k], g[k]);
-                }
-            }
-        } else if (valid) {
-            if (in_ring) {
-#pragma unroll
-                for (int k = 0; k < kG; ++k) atomicAdd(&acc[sl][k], g[k]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < kG; ++k) unsafeAtomicAdd(&vgrad[size_t(gid) * kG + k], g[k]);
+            for (int k = 0; k < kG; ++k) {
+                if (g[k] == 0.f) continue;
+                if (!in_ring || !fixed_add(&acc[sl][k], &acc_scale[sl][k], g[k])) unsafeAtomicAdd(dst + k, g[k]);
             }
         }
     };
@@ -285,8 +299,9 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             // Flush the batch that leaves the ring.
             for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
                 const int s = base + w / kG, k = w % kG;
-                const float val = acc[s][k];
-                if (val != 0.f) unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], val);
+                const int sc = acc_scale[s][k];
+                if (sc != kUnset && acc[s][k] != 0ull)
+                    unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], fixed_value(acc[s][k], sc));
             }
             __syncthreads();
             ring_lo = b0 + kBwdBatch - kRing;
@@ -301,7 +316,10 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             ring_box[base + t] = rec[7];
             ring_gid[base + t] = gid;
         }
-        for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) acc[base + w / kG][w % kG] = 0.f;
+        for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
+            acc[base + w / kG][w % kG] = 0ull;
+            acc_scale[base + w / kG][w % kG] = kUnset;
+        }
         last_b0 = b0;
         staged_end = b0 + uint32_t(nb);
         __syncthreads();
@@ -357,8 +375,9 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         const int s = w / kG, k = w % kG;
         const uint32_t a = first + (uint32_t(s) + uint32_t(kRing) - first % uint32_t(kRing)) % uint32_t(kRing);
         if (a >= staged_end) continue;
-        const float val = acc[s][k];
-        if (val != 0.f) unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], val);
+        const int sc = acc_scale[s][k];
+        if (sc != kUnset && acc[s][k] != 0ull)
+            unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], fixed_value(acc[s][k], sc));
     }
 }
 
@@ -454,40 +473,6 @@ __device__ inline void splat_params(const Dual mu[3], const Dual ls[3], const Du
     xy[1] = double(V.cy) + V.f * (muc[1] / muc[2]);
 }
 
-// Real SH basis (the polynomials of sh_eval) at a dual unit direction.
-__device__ inline void sh_basis_dual(int K, const Dual v[3], Dual Y[16]) {
-    const Dual x = v[0], y = v[1], z = v[2];
-    constexpr double pi = M_PI;
-    Y[0] = dconst(0.5 / sqrt(pi));
-    if (K > 1) {
-        const double c1 = sqrt(3.0 / (4.0 * pi));
-        Y[1] = -(c1 * y);
-        Y[2] = c1 * z;
-        Y[3] = -(c1 * x);
-    }
-    if (K > 4) {
-        const double c2a = sqrt(15.0 / (4.0 * pi)), c2b = sqrt(5.0 / (16.0 * pi)), c2c = sqrt(15.0 / (16.0 * pi));
-        Y[4] = c2a * (x * y);
-        Y[5] = -(c2a * (y * z));
-        Y[6] = c2b * (3.0 * (z * z) - dconst(1.0));
-        Y[7] = -(c2a * (x * z));
-        Y[8] = c2c * (x * x - y * y);
-    }
-    if (K > 9) {
-        const double c3a = sqrt(35.0 / (32.0 * pi)), c3b = sqrt(105.0 / (4.0 * pi));
-        const double c3c = sqrt(21.0 / (32.0 * pi)), c3d = sqrt(7.0 / (16.0 * pi));
-        const double c3e = sqrt(105.0 / (16.0 * pi));
-        const Dual xx = x * x, yy = y * y, zz = z * z;
-        Y[9] = -(c3a * (y * (3.0 * xx - yy)));
-        Y[10] = c3b * (x * y * z);
-        Y[11] = -(c3c * (y * (5.0 * zz - dconst(1.0))));
-        Y[12] = c3d * (z * (5.0 * zz - dconst(3.0)));
-        Y[13] = -(c3c * (x * (5.0 * zz - dconst(1.0))));
-        Y[14] = c3e * (z * (xx - yy));
-        Y[15] = -(c3a * (x * (xx - 3.0 * yy)));
-    }
-}
-
 // Gradient of one Gaussian's render-record gradients of view v (12 floats).
 __device__ inline void load_g12(const float* grad2d, int v, int n, int i, float gv[kG]) {
     const float4* gg = reinterpret_cast<const float4*>(grad2d + (size_t(v) * n + i) * kG);
@@ -497,9 +482,69 @@ __device__ inline void load_g12(const float* grad2d, int v, int n, int i, float 
     gv[8] = c.x; gv[9] = c.y; gv[10] = c.z; gv[11] = c.w;
 }
 
+// Value and gradient (d/dx, d/dy, d/dz) of a polynomial in the direction.
+struct Grad3 {
+    float v, x, y, z;
+};
+__device__ inline Grad3 g3(float v, float x, float y, float z) { return Grad3{v, x, y, z}; }
+
+// Real SH basis function k (the polynomials of sh_basis) and its gradient
+// with respect to the (unnormalised) polynomial variables x, y, z.
+__device__ inline Grad3 sh_basis_grad(int k, float x, float y, float z) {
+    constexpr double pi = M_PI;
+    switch (k) {
+        case 0: return g3(float(0.5 / sqrt(pi)), 0.f, 0.f, 0.f);
+        case 1: { const float c = float(sqrt(3.0 / (4.0 * pi))); return g3(-c * y, 0.f, -c, 0.f); }
+        case 2: { const float c = float(sqrt(3.0 / (4.0 * pi))); return g3(c * z, 0.f, 0.f, c); }
+        case 3: { const float c = float(sqrt(3.0 / (4.0 * pi))); return g3(-c * x, -c, 0.f, 0.f); }
+        case 4: { const float c = float(sqrt(15.0 / (4.0 * pi))); return g3(c * x * y, c * y, c * x, 0.f); }
+        case 5: { const float c = float(sqrt(15.0 / (4.0 * pi))); return g3(-c * y * z, 0.f, -c * z, -c * y); }
+        case 6: {
+            const float c = float(sqrt(5.0 / (16.0 * pi)));
+            return g3(c * (3.f * z * z - 1.f), 0.f, 0.f, 6.f * c * z);
+        }
+        case 7: { const float c = float(sqrt(15.0 / (4.0 * pi))); return g3(-c * x * z, -c * z, 0.f, -c * x); }
+        case 8: {
+            const float c = float(sqrt(15.0 / (16.0 * pi)));
+            return g3(c * (x * x - y * y), 2.f * c * x, -2.f * c * y, 0.f);
+        }
+        case 9: {
+            const float c = float(sqrt(35.0 / (32.0 * pi)));
+            return g3(-c * y * (3.f * x * x - y * y), -6.f * c * x * y, -c * (3.f * x * x - 3.f * y * y), 0.f);
+        }
+        case 10: {
+            const float c = float(sqrt(105.0 / (4.0 * pi)));
+            return g3(c * x * y * z, c * y * z, c * x * z, c * x * y);
+        }
+        case 11: {
+            const float c = float(sqrt(21.0 / (32.0 * pi)));
+            return g3(-c * y * (5.f * z * z - 1.f), 0.f, -c * (5.f * z * z - 1.f), -10.f * c * y * z);
+        }
+        case 12: {
+            const float c = float(sqrt(7.0 / (16.0 * pi)));
+            return g3(c * z * (5.f * z * z - 3.f), 0.f, 0.f, c * (15.f * z * z - 3.f));
+        }
+        case 13: {
+            const float c = float(sqrt(21.0 / (32.0 * pi)));
+            return g3(-c * x * (5.f * z * z - 1.f), -c * (5.f * z * z - 1.f), 0.f, -10.f * c * x * z);
+        }
+        case 14: {
+            const float c = float(sqrt(105.0 / (16.0 * pi)));
+            return g3(c * z * (x * x - y * y), 2.f * c * x * z, -2.f * c * y * z, c * (x * x - y * y));
+        }
+        default: {
+            const float c = float(sqrt(35.0 / (32.0 * pi)));
+            return g3(-c * x * (x * x - 3.f * y * y), -c * (3.f * x * x - 3.f * y * y), 6.f * c * x * y, 0.f);
+        }
+    }
+}
+
 // K8b, colour part: SH coefficients, and the mean through the view
-// direction.  Writes out.sh and out.means (the geometry part adds to the
-// latter).
+// direction.  colour_c = max(0, sum_k sh_kc Y_k(u) + 0.5) with u = d / |d|,
+// d = mean - eye centre: dL/dsh_kc = g_c Y_k(u) where the colour is not
+// clamped, and dL/dmean = J_u^T sum_c g_c grad Y . sh_c with
+// J_u = (I - u u^T) / |d|.  One thread per Gaussian; writes out.sh and
+// out.means (the geometry part adds to the latter).
 __global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, const float* __restrict__ grad2d,
                                                    GradPtrs out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -510,50 +555,63 @@ __global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, 
     float gsh[16][3];
 #pragma unroll
     for (int k = 0; k < 16; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
-    double gm[3] = {0.0, 0.0, 0.0};
+    float gm[3] = {0.f, 0.f, 0.f};
     for (int v = 0; v < views.n; ++v) {
         const GeoView& V = views.v[v];
         const float4 gc = reinterpret_cast<const float4*>(grad2d + (size_t(v) * n + i) * kG)[2];
         const float grgb[3] = {gc.y, gc.z, gc.w};
         if (grgb[0] == 0.f && grgb[1] == 0.f && grgb[2] == 0.f) continue;
-        // colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = unit vector from
-        // the eye centre o = -R^T t to the mean.
         double dir[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
             dir[c] = mu[c] + (double(V.R[c]) * V.t[0] + double(V.R[3 + c]) * V.t[1] + double(V.R[6 + c]) * V.t[2]);
-#pragma unroll 1
-        for (int pi = 0; pi < 3; ++pi) {
-            Dual d[3];
-            for (int c = 0; c < 3; ++c) d[c] = Dual{dir[c], pi == c ? 1.0 : 0.0};
-            const Dual dn = dsqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            const Dual u[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
-            Dual Y[16];
-            sh_basis_dual(K, u, Y);
-            double s = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                Dual col = dconst(0.5);
+        const double dn = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        const float u[3] = {float(dir[0] / dn), float(dir[1] / dn), float(dir[2] / dn)};
+        // Colour values and gradients with respect to u.
+        Grad3 col[3] = {g3(0.5f, 0.f, 0.f, 0.f), g3(0.5f, 0.f, 0.f, 0.f), g3(0.5f, 0.f, 0.f, 0.f)};
 #pragma unroll
-                for (int k = 0; k < 16; ++k)
-                    if (k < K) col = col + double(g.sh[(k * 3 + c) * n + i]) * Y[k];
-                if (col.v > 0.0) {  // a clamped colour passes no gradient
-                    s += double(grgb[c]) * col.d;
-                    if (pi == 0) {
+        for (int k = 0; k < 16; ++k) {
+            if (k < K) {
+                const Grad3 y = sh_basis_grad(k, u[0], u[1], u[2]);
 #pragma unroll
-                        for (int k = 0; k < 16; ++k)
-                            if (k < K) gsh[k][c] += grgb[c] * float(Y[k].v);
-                    }
+                for (int c = 0; c < 3; ++c) {
+                    const float a = g.sh[(k * 3 + c) * n + i];
+                    col[c].v = fmaf(a, y.v, col[c].v);
+                    col[c].x = fmaf(a, y.x, col[c].x);
+                    col[c].y = fmaf(a, y.y, col[c].y);
+                    col[c].z = fmaf(a, y.z, col[c].z);
                 }
             }
-            gm[pi] += s;
+        }
+        float wc[3], gu[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            wc[c] = col[c].v > 0.f ? grgb[c] : 0.f;  // a clamped colour passes no gradient
+            gu[0] = fmaf(wc[c], col[c].x, gu[0]);
+            gu[1] = fmaf(wc[c], col[c].y, gu[1]);
+            gu[2] = fmaf(wc[c], col[c].z, gu[2]);
+        }
+        // Through u = d / |d|: dL/dd = (gu - (gu . u) u) / |d|.
+        const float gdotu = gu[0] * u[0] + gu[1] * u[1] + gu[2] * u[2];
+        const float idn = float(1.0 / dn);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gm[c] = fmaf(gu[c] - gdotu * u[c], idn, gm[c]);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const float yv = sh_basis_grad(k, u[0], u[1], u[2]).v;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gsh[k][c] = fmaf(wc[c], yv, gsh[k][c]);
         }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out.means[c * n + i] = float(gm[c]);
+    for (int c = 0; c < 3; ++c) out.means[c * n + i] = gm[c];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-        if (k < K)
+    for (int k = 0; k < 16; ++k) {
+        if (k < K) {
+#pragma unroll
             for (int c = 0; c < 3; ++c) out.sh[(k * 3 + c) * n + i] = gsh[k][c];
+        }
+    }
 }
 
 // K8b, geometry part: means (added to the colour part), log-scales,

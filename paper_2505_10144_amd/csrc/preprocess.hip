@@ -15,48 +15,35 @@ namespace vrs {
 
 // Real spherical harmonics (orthonormal, Condon-Shortley phase) up to degree
 // 3 written as polynomials of the unit direction (x, y, z), k = l^2 + l + m.
-__device__ inline void sh_eval(const GaussPtrs& g, int i, const float v[3], float rgb[3]) {
-    const int n = g.n;
-    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+__device__ inline void sh_basis(const float v[3], float Y[16]) {
     const float x = v[0], y = v[1], z = v[2];
     constexpr double pi = M_PI;
-    float Y[16];
-    Y[0] = float(0.5 / sqrt(pi));
-    if (K > 1) {
-        const float c1 = float(sqrt(3.0 / (4.0 * pi)));
-        Y[1] = -c1 * y;
-        Y[2] = c1 * z;
-        Y[3] = -c1 * x;
-    }
-    if (K > 4) {
-        const float c2a = float(sqrt(15.0 / (4.0 * pi)));   // xy, yz, xz terms
-        const float c2b = float(sqrt(5.0 / (16.0 * pi)));   // 3z^2 - 1
-        const float c2c = float(sqrt(15.0 / (16.0 * pi)));  // x^2 - y^2
-        Y[4] = c2a * x * y;
-        Y[5] = -c2a * y * z;
-        Y[6] = c2b * (3.f * z * z - 1.f);
-        Y[7] = -c2a * x * z;
-        Y[8] = c2c * (x * x - y * y);
-    }
-    if (K > 9) {
-        const float c3a = float(sqrt(35.0 / (32.0 * pi)));   // |m| = 3
-        const float c3b = float(sqrt(105.0 / (4.0 * pi)));   // m = -2: xyz
-        const float c3c = float(sqrt(21.0 / (32.0 * pi)));   // |m| = 1
-        const float c3d = float(sqrt(7.0 / (16.0 * pi)));    // m = 0
-        const float c3e = float(sqrt(105.0 / (16.0 * pi)));  // m = 2
-        Y[9] = -c3a * y * (3.f * x * x - y * y);
-        Y[10] = c3b * x * y * z;
-        Y[11] = -c3c * y * (5.f * z * z - 1.f);
-        Y[12] = c3d * z * (5.f * z * z - 3.f);
-        Y[13] = -c3c * x * (5.f * z * z - 1.f);
-        Y[14] = c3e * z * (x * x - y * y);
-        Y[15] = -c3a * x * (x * x - 3.f * y * y);
-    }
-    for (int c = 0; c < 3; ++c) {
-        float acc = 0.5f;
-        for (int k = 0; k < K; ++k) acc = fmaf(g.sh[(k * 3 + c) * n + i], Y[k], acc);
-        rgb[c] = fmaxf(acc, 0.f);
-    }
+    const float c0 = float(0.5 / sqrt(pi));
+    const float c1 = float(sqrt(3.0 / (4.0 * pi)));
+    const float c2a = float(sqrt(15.0 / (4.0 * pi)));   // xy, yz, xz terms
+    const float c2b = float(sqrt(5.0 / (16.0 * pi)));   // 3z^2 - 1
+    const float c2c = float(sqrt(15.0 / (16.0 * pi)));  // x^2 - y^2
+    const float c3a = float(sqrt(35.0 / (32.0 * pi)));   // |m| = 3
+    const float c3b = float(sqrt(105.0 / (4.0 * pi)));   // m = -2: xyz
+    const float c3c = float(sqrt(21.0 / (32.0 * pi)));   // |m| = 1
+    const float c3d = float(sqrt(7.0 / (16.0 * pi)));    // m = 0
+    const float c3e = float(sqrt(105.0 / (16.0 * pi)));  // m = 2
+    Y[0] = c0;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    Y[4] = c2a * x * y;
+    Y[5] = -c2a * y * z;
+    Y[6] = c2b * (3.f * z * z - 1.f);
+    Y[7] = -c2a * x * z;
+    Y[8] = c2c * (x * x - y * y);
+    Y[9] = -c3a * y * (3.f * x * x - y * y);
+    Y[10] = c3b * x * y * z;
+    Y[11] = -c3c * y * (5.f * z * z - 1.f);
+    Y[12] = c3d * z * (5.f * z * z - 3.f);
+    Y[13] = -c3c * x * (5.f * z * z - 1.f);
+    Y[14] = c3e * z * (x * x - y * y);
+    Y[15] = -c3a * x * (x * x - 3.f * y * y);
 }
 
 __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views, Knobs kn,
@@ -102,26 +89,54 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
 
 // View-dependent colour of every Gaussian in every view from its SH
 // coefficients (kept apart from k_preprocess so that the 48 coefficients do
-// not occupy registers across the FP64 set-up).  Culled Gaussian-views get a
-// colour too; no list refers to them.
+// not occupy registers across the FP64 set-up).  Views go in groups of four:
+// each coefficient is read once per group and applied to all of its views,
+// so a stereo pair reads the coefficients from HBM once.  Culled
+// Gaussian-views get a colour too; no list refers to them.
+constexpr int kColorViews = 4;
+
 __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, float* __restrict__ proj) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
-    const double mu[3] = {double(g.means[i]), double(g.means[g.n + i]), double(g.means[2 * g.n + i])};
-    for (int v = 0; v < views.n; ++v) {
-        const GeoView& V = views.v[v];
-        // Direction from the eye centre o = -R^T t to the mean.
-        double dir[3];
-        for (int c = 0; c < 3; ++c)
-            dir[c] = mu[c] + (double(V.R[c]) * V.t[0] + double(V.R[3 + c]) * V.t[1] + double(V.R[6 + c]) * V.t[2]);
-        const double idn = 1.0 / sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-        const float fd[3] = {float(dir[0] * idn), float(dir[1] * idn), float(dir[2] * idn)};
-        float rgb[3];
-        sh_eval(g, i, fd, rgb);
-        float* dst = proj + (size_t(v) * size_t(g.n) + size_t(i)) * kRec + R_RGB;
-        dst[0] = rgb[0];
-        dst[1] = rgb[1];
-        dst[2] = rgb[2];
+    const int n = g.n;
+    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    const double mu[3] = {double(g.means[i]), double(g.means[n + i]), double(g.means[2 * n + i])};
+    for (int v0 = 0; v0 < views.n; v0 += kColorViews) {
+        float Y[kColorViews][16];
+        float rgb[kColorViews][3];
+#pragma unroll
+        for (int j = 0; j < kColorViews; ++j) {
+            const int v = min(v0 + j, views.n - 1);
+            const GeoView& V = views.v[v];
+            // Direction from the eye centre o = -R^T t to the mean.
+            double dir[3];
+            for (int c = 0; c < 3; ++c)
+                dir[c] = mu[c] + (double(V.R[c]) * V.t[0] + double(V.R[3 + c]) * V.t[1] + double(V.R[6 + c]) * V.t[2]);
+            const double idn = 1.0 / sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+            const float fd[3] = {float(dir[0] * idn), float(dir[1] * idn), float(dir[2] * idn)};
+            sh_basis(fd, Y[j]);
+            rgb[j][0] = rgb[j][1] = rgb[j][2] = 0.5f;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < K) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float a = g.sh[(k * 3 + c) * n + i];
+#pragma unroll
+                    for (int j = 0; j < kColorViews; ++j) rgb[j][c] = fmaf(a, Y[j][k], rgb[j][c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kColorViews; ++j) {
+            if (v0 + j < views.n) {
+                float* dst = proj + (size_t(v0 + j) * size_t(n) + size_t(i)) * kRec + R_RGB;
+                dst[0] = fmaxf(rgb[j][0], 0.f);
+                dst[1] = fmaxf(rgb[j][1], 0.f);
+                dst[2] = fmaxf(rgb[j][2], 0.f);
+            }
+        }
     }
 }
 

@@ -135,6 +135,21 @@ def test_backward_long_lists_leave_the_ring(R):
     compare_grads(got, ref, 16)
 
 
+def test_backward_upstream_spanning_many_octaves(R):
+    """Upstream gradients log-uniform over 1e-4 .. 1e6 with random signs: an
+    entry's contributions span far more than the fixed-point accumulators'
+    headroom over their first contribution, so the overflow path (direct
+    float atomics) is taken as well as the accumulators."""
+    scene, cams = cluster_views(8, 3000, (80, 64), n_views=1)
+    params = synth.default_params(tile=16, window=16)
+    rng = np.random.default_rng(8)
+    Wt = [np.exp(rng.uniform(np.log(1e-4), np.log(1e6), (4, c.height, c.width)))
+          * rng.choice([-1.0, 1.0], (4, c.height, c.width)) for c in cams]
+    ref, res, used = ograd.vjp(scene, cams, params, Wt, workers=8, mask_flagged=True)
+    got, _ = gpu_vjp(R, scene, cams, params, used)
+    compare_grads(got, ref, 16)
+
+
 def test_backward_all_culled(R):
     scene, cams = cluster_views(6, 500, (64, 48), n_views=1)
     scene.opacity_logits[:] = np.float32(-10.0)  # opacity below alpha_min: all culled
