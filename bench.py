@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--diff-only", action="store_true", help="run only the fwd+bwd leg (for profiling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched multi-view leg")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched multi-view leg")
+    ap.add_argument("--batch-knobs", default=None,
+                    help="tile,window,blend_batch,schedule for the batch leg instead of the autotuner's choice")
     ap.add_argument("--cpu-tiles", type=int, default=24, help="32x32 tiles per eye in the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -175,7 +177,7 @@ def diff_leg(steps, warmup):
             "n_gaussians": scene.n, "views": V}
 
 
-def batch_leg(steps, log=None):
+def batch_leg(steps, log=None, knobs=None):
     """The batched multi-view form: 1M cluster Gaussians rendered to 16 views
     of mixed size (4 each of 512^2, 1024^2, 1920x1080, 2064x2208) and FoV, a
     random half foveated, in one call sequence (one preprocess, one sort, one
@@ -191,9 +193,13 @@ def batch_leg(steps, log=None):
     g = upload(scene)
     cache = os.environ.get("VRS_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "vrs_tune_cache.json"))
     t0 = time.perf_counter()
-    res = tune(g, cams, fovs, params, cache_path=cache, steps=3, log=log)
+    if knobs:
+        tile, window, bb, sc = (int(x) for x in knobs.split(","))
+        p, cached = params.replace(tile=tile, window=window, blend_batch=bb, schedule=sc), None
+    else:
+        res = tune(g, cams, fovs, params, cache_path=cache, steps=3, log=log)
+        p, cached = res.params, res.cached
     t_tune = time.perf_counter() - t0
-    p = res.params
     r = Renderer(cams, fovs, p, scene.n)
     r.ensure_capacity(g)
     batched = time_frames(r, g, steps)
@@ -210,7 +216,7 @@ def batch_leg(steps, log=None):
     return {"batched_ms": round(batched, 4), "separate_ms": round(sep, 4),
             "speedup": round(sep / batched, 3), "views": len(cams), "items": n_items,
             "tuned": {k: getattr(p, k) for k in ("tile", "window", "blend_batch", "schedule")},
-            "tune_s": round(t_tune, 1), "tune_cached": res.cached,
+            "tune_s": round(t_tune, 1), "tune_cached": cached, "tune_cache": cache,
             "workload": "batch: 1M cluster Gaussians, 16 views (4 each 512^2, 1024^2, 1920x1080, 2064x2208), "
                         "FoV U[60,120] deg, 8 foveated (15 deg)"}
 
@@ -234,8 +240,8 @@ def main():
         print(json.dumps({"fwd_bwd": diff_leg(args.diff_steps, 3)}), flush=True)
         return
     if args.batch_only:
-        print(json.dumps({"batch": batch_leg(5, log=lambda row: print(row, file=sys.stderr, flush=True))}),
-              flush=True)
+        print(json.dumps({"batch": batch_leg(5, log=lambda row: print(row, file=sys.stderr, flush=True),
+                                             knobs=args.batch_knobs)}), flush=True)
         return
     scene, cams, fovs, params = synth.config_stereo(0, n=args.n, window=args.window)
     params = params.replace(schedule=args.schedule, blend_batch=args.blend_batch)
@@ -312,7 +318,7 @@ def main():
         out["fwd_bwd"] = diff_leg(args.diff_steps, 3)
         torch.cuda.empty_cache()
     if not args.no_batch:
-        out["batch"] = batch_leg(5)
+        out["batch"] = batch_leg(5, knobs=args.batch_knobs)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams, fovs, params, n_items, args.cpu_tiles)

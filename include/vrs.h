@@ -251,11 +251,13 @@ int vrs_compose(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views
                 const vrs_params* p, const void* plan, float* const* rgba, void* ws,
                 size_t ws_bytes, vrs_stream_t stream);
 
-/* Instrumented vrs_blend (same output) that also adds to counters_dev[5]
+/* Instrumented vrs_blend (same output) that also adds to counters_dev[6]
  * (uint64, caller-zeroed): [0] evaluated (sample, list entry) pairs, [1]
  * pairs whose alpha reaches alpha_min, [2] in-image samples, [3] samples
- * stopped by t_min, [4] list entries staged by the waves.  These are the
- * work units of the blending roofline; it runs slower than vrs_blend. */
+ * stopped by t_min, [4] list entries staged by the waves, [5] wave-level
+ * window insertion steps (each runs the insertion network on all 64
+ * lanes).  These are the work units of the blending roofline; it runs
+ * slower than vrs_blend. */
 int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
                     const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
                     const vrs_params* p, const void* plan, uint32_t n_items,

@@ -31,6 +31,7 @@ int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 constexpr int kRenderThreads = 256;
 constexpr int kBatch = 64;      // entries staged per wave and batch
 constexpr int kStage = 7;       // float4 per staged entry
+constexpr int kInbox = 8;       // entries a lane collects before the wave drains
 
 struct Slot {
     float t, a, r, g, b;
@@ -121,11 +122,26 @@ __device__ inline void wave_sync_lds() {
 // time.  STATS = true is the instrumented variant: it also counts evaluated
 // (sample, entry) pairs, pairs that reach alpha_min, in-image samples,
 // samples stopped by t_min and list entries staged.
+//
+// Window insertions are batched per lane: an entry that reaches alpha_min at
+// a sample goes into the lane's inbox (LDS, its own column), and when some
+// lane's inbox is full the wave drains every lane's inbox through the
+// window in arrival order.  Each lane therefore pushes exactly the entries,
+// in exactly the order, of an immediate insertion -- the output is the same
+// bit for bit -- but the insertion network, which runs on all 64 lanes
+// whenever any lane inserts, runs about as often as the busiest lane
+// inserts rather than once per entry that any lane inserts.  A lane whose
+// transmittance has fallen below t_min is only found to have stopped at the
+// next drain; the entries it collects meanwhile are then skipped.  The
+// instrumented variant inserts immediately (an inbox of one), so that its
+// counters measure the algorithm's work.
 template <int W, bool STATS>
-__device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], const float* __restrict__ proj,
-                                   uint32_t n_gauss, const uint32_t* __restrict__ gids,
-                                   const uint32_t* __restrict__ ranges, const RenderViews& views, const Knobs& kn,
-                                   int batch, unsigned long long* __restrict__ stats) {
+__device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], float4 (*ib)[64], float (*ibb)[64],
+                                   const float* __restrict__ proj, uint32_t n_gauss,
+                                   const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges,
+                                   const RenderViews& views, const Knobs& kn, int batch,
+                                   unsigned long long* __restrict__ stats) {
+    constexpr int kCap = STATS ? 1 : kInbox;
     const int v = item_view(item);
     const int cls = item_class(item);
     const int sub = item_sub(item);
@@ -166,7 +182,8 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
     const float amax = kn.alpha_max, tmin = kn.t_min;
-    uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0;
+    uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0, n_push = 0;
+    int cnt = 0;  // entries in this lane's inbox
 
     // This wave's samples lie in a pixel rectangle; list entries whose box
     // misses it cannot reach alpha_min at any of them and are skipped for
@@ -182,35 +199,51 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
         ry0 = float(oy + by + 4 * wv) + 0.5f; ry1 = float(oy + by + 4 * wv) + 3.5f;
     }
 
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += uint32_t(batch)) {
-        if (__ballot(acc.alive) == 0ull) break;
-        const int nb = int(min(uint32_t(batch), rg.y - b0));
-        bool rel = false;
-        if (lane < nb) {
-            const uint32_t gid = gids[b0 + lane];
-            const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
-            const float4 p7 = rec[7];
-            rel = !(p7.z < rx0 || p7.x > rx1 || p7.w < ry0 || p7.y > ry1);
-            if (rel) {
-                const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
-                const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
-                // Mean offset relative to the tile origin, split so that the
-                // integer part is exact: (ox - x0i) - x0f.
-                const float ex = float(ox - int(p0.x)) - p0.z;
-                const float ey = float(oy - int(p0.y)) - p0.w;
-                st[lane][0] = make_float4(ex, ey, p1.x, p1.y);          // M00 M01
-                st[lane][1] = make_float4(p1.z, p1.w, p2.x, p2.y);      // M10 M11 a3x a3y
-                st[lane][2] = make_float4(p2.z, p2.w, p3.x, p3.y);      // l2s kap n0 nx
-                st[lane][3] = make_float4(p3.z, p4.x, p4.y, p4.z);      // ny w0
-                st[lane][4] = make_float4(p4.w, p5.x, p5.y, p5.z);      // wx wy.x
-                st[lane][5] = make_float4(p5.w, p6.x, p6.y, p6.z);      // wy.yz r g
-                st[lane][6] = make_float4(p6.w, 0.f, 0.f, 0.f);         // b
+    // Collect entries into the inboxes until some lane's inbox is full or the
+    // list ends, then push every lane's inbox through its window in arrival
+    // order; repeat.  A single drain site keeps the window's registers apart
+    // from the collecting loop's.
+    uint32_t b0 = rg.x;          // first list entry of the staged batch
+    uint64_t todo = 0;           // staged entries of the batch still to test
+    bool staged = false;         // a batch is staged in this wave's slice
+    for (;;) {
+        bool full = false;
+        for (;;) {
+            if (todo == 0ull) {
+                if (staged) {
+                    wave_sync_lds();
+                    b0 += uint32_t(batch);
+                }
+                if (b0 >= rg.y || __ballot(acc.alive) == 0ull) break;
+                const int nb = int(min(uint32_t(batch), rg.y - b0));
+                bool rel = false;
+                if (lane < nb) {
+                    const uint32_t gid = gids[b0 + lane];
+                    const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
+                    const float4 p7 = rec[7];
+                    rel = !(p7.z < rx0 || p7.x > rx1 || p7.w < ry0 || p7.y > ry1);
+                    if (rel) {
+                        const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
+                        const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
+                        // Mean offset relative to the tile origin, split so that
+                        // the integer part is exact: (ox - x0i) - x0f.
+                        const float ex = float(ox - int(p0.x)) - p0.z;
+                        const float ey = float(oy - int(p0.y)) - p0.w;
+                        st[lane][0] = make_float4(ex, ey, p1.x, p1.y);          // M00 M01
+                        st[lane][1] = make_float4(p1.z, p1.w, p2.x, p2.y);      // M10 M11 a3x a3y
+                        st[lane][2] = make_float4(p2.z, p2.w, p3.x, p3.y);      // l2s kap n0 nx
+                        st[lane][3] = make_float4(p3.z, p4.x, p4.y, p4.z);      // ny w0
+                        st[lane][4] = make_float4(p4.w, p5.x, p5.y, p5.z);      // wx wy.x
+                        st[lane][5] = make_float4(p5.w, p6.x, p6.y, p6.z);      // wy.yz r g
+                        st[lane][6] = make_float4(p6.w, 0.f, 0.f, 0.f);         // b
+                    }
+                }
+                todo = __ballot(rel);
+                staged = true;
+                if (STATS) n_staged += uint32_t(__popcll(todo));
+                wave_sync_lds();
+                continue;
             }
-        }
-        uint64_t todo = __ballot(rel);
-        if (STATS) n_staged += uint32_t(__popcll(todo));
-        wave_sync_lds();
-        while (todo) {
             const int j = __builtin_ctzll(todo);
             todo &= todo - 1;
             const float4 f0 = st[j][0], f1 = st[j][1], f2 = st[j][2];
@@ -225,23 +258,41 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
                 n_pairs += acc.alive ? 1u : 0u;
                 n_contrib += pass ? 1u : 0u;
             }
-            if (__ballot(pass) != 0ull) {  // wave-uniform
+            if (pass) {
                 const float4 f3 = st[j][3], f4 = st[j][4], f5 = st[j][5], f6 = st[j][6];
-                Slot x;
-                x.a = pass ? fminf(amax, exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2))) : 0.f;
+                const float a = fminf(amax, exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2)));
                 const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
                 const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
                 const float w1 = fmaf(f4.y, dx, fmaf(f5.x, dy, f3.z));
                 const float w2 = fmaf(f4.z, dx, fmaf(f5.y, dy, f3.w));
                 const float den = fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
-                x.t = pass ? num * __builtin_amdgcn_rcpf(den) : -INFINITY;
-                x.r = f5.z; x.g = f5.w; x.b = f6.x;
-                const Slot e = win.push(x);
-                acc.blend(e.a, e.r, e.g, e.b, tmin);
+                const float t = num * __builtin_amdgcn_rcpf(den);
+                ib[cnt][lane] = make_float4(t, a, f5.z, f5.w);
+                ibb[cnt][lane] = f6.x;
+                ++cnt;
             }
-            if (__ballot(acc.alive) == 0ull) break;
+            if (__ballot(cnt >= kCap) != 0ull) {  // wave-uniform
+                full = true;
+                break;
+            }
         }
-        wave_sync_lds();
+        // Drain: every lane pushes its inbox through its window in order.
+#pragma unroll 1
+        for (int i = 0; i < kCap; ++i) {
+            const bool has = i < cnt;
+            if (__ballot(has) == 0ull) break;  // wave-uniform
+            if (STATS) ++n_push;
+            Slot x;
+            x.t = -INFINITY; x.a = 0.f; x.r = 0.f; x.g = 0.f; x.b = 0.f;
+            if (has) {
+                const float4 v4 = ib[i][lane];
+                x.t = v4.x; x.a = v4.y; x.r = v4.z; x.g = v4.w; x.b = ibb[i][lane];
+            }
+            const Slot e = win.push(x);
+            acc.blend(e.a, e.r, e.g, e.b, tmin);
+        }
+        cnt = 0;
+        if (!full || __ballot(acc.alive) == 0ull) break;
     }
     // Flush the window in ascending depth order.
 #pragma unroll
@@ -257,6 +308,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
         if (lane == 0) {
             for (int k = 0; k < 4; ++k) atomicAdd(&stats[k], c[k]);
             atomicAdd(&stats[4], (unsigned long long)n_staged);
+            atomicAdd(&stats[5], (unsigned long long)n_push);
         }
     }
     float o[4] = {acc.cr + acc.T * kn.bg[0], acc.cg + acc.T * kn.bg[1], acc.cb + acc.T * kn.bg[2], 1.f - acc.T};
@@ -314,10 +366,12 @@ k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __res
          uint32_t* __restrict__ counter, int batch, RenderViews views, Knobs kn,
          unsigned long long* __restrict__ stats) {
     __shared__ float4 stage[kRenderThreads / 64][kBatch][kStage];
+    __shared__ float4 inbox[kRenderThreads / 64][kInbox][64];
+    __shared__ float inbox_b[kRenderThreads / 64][kInbox][64];
     const int slot = int(threadIdx.x) >> 6;
     if (!PERSIST) {
-        render_unit<W, STATS>(items[blockIdx.x], slot, stage[slot], proj, n_gauss, gids, ranges, views, kn, batch,
-                              stats);
+        render_unit<W, STATS>(items[blockIdx.x], slot, stage[slot], inbox[slot], inbox_b[slot], proj, n_gauss, gids,
+                              ranges, views, kn, batch, stats);
         return;
     }
     const int lane = int(threadIdx.x) & 63;
@@ -327,8 +381,8 @@ k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __res
         if (lane == 0) u = atomicAdd(counter, 1u);
         u = __shfl(u, 0);
         if (u >= n_units) break;
-        render_unit<W, STATS>(items[u >> 2], int(u & 3u), stage[slot], proj, n_gauss, gids, ranges, views, kn, batch,
-                              stats);
+        render_unit<W, STATS>(items[u >> 2], int(u & 3u), stage[slot], inbox[slot], inbox_b[slot], proj, n_gauss,
+                              gids, ranges, views, kn, batch, stats);
     }
 }
 

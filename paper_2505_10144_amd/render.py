@@ -180,13 +180,13 @@ class Renderer:
 
     def blend_stats(self):
         """Instrumented blend: returns dict of work counters (one sync)."""
-        c = torch.zeros(5, dtype=torch.int64, device=self.device)
+        c = torch.zeros(6, dtype=torch.int64, device=self.device)
         L.call("vrs_blend_stats", _ptr(self.proj), self.n, _ptr(self.gids), _ptr(self.ranges),
                self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), _ptr(self.plan),
                ctypes.c_uint32(self.n_items), self._img_ptrs, _ptr(self.render_ws),
                ctypes.c_size_t(self.render_ws.numel()), _ptr(c), _stream(self.stream))
         v = c.cpu().tolist()
-        return dict(pairs=v[0], contrib=v[1], samples=v[2], stopped=v[3], staged=v[4])
+        return dict(pairs=v[0], contrib=v[1], samples=v[2], stopped=v[3], staged=v[4], push_steps=v[5])
 
     def blend(self):
         L.call("vrs_render_foveated", _ptr(self.proj), self.n, _ptr(self.gids), _ptr(self.ranges),

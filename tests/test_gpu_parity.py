@@ -168,6 +168,24 @@ def test_schedules_and_batches_are_bit_identical(R):
                 assert np.array_equal(a, b), (schedule, batch)
 
 
+@pytest.mark.parametrize("window", [4, 16])
+def test_inbox_blend_equals_immediate_insertion(R, window):
+    """The blend batches window insertions through per-lane inboxes; the
+    instrumented blend inserts immediately.  Both give the same bits."""
+    scene = synth.cluster_scene(6, 30000, log_scale=(-4.5, 0.6))
+    rng = np.random.default_rng(10)
+    cams = synth.ring_cameras(rng, 2, 3.0, [(224, 176)])
+    fovs = [synth.fovea_off(), synth.fovea_at_center(cams[1], 15.0)]
+    params = synth.default_params(tile=16, window=window)
+    r, g, imgs = run_gpu(R, scene, cams, fovs, params)
+    work = r.blend_stats()
+    r.compose()
+    torch.cuda.synchronize()
+    for a, b in zip(imgs, r.images):
+        assert np.array_equal(a, b.cpu().numpy().astype(np.float64))
+    assert work["push_steps"] > 0 and work["contrib"] > 0
+
+
 def test_deterministic_repeat(R):
     scene, cams, fovs, params = synth.config_stereo(2, n=20000, width=320, height=288)
     r, g, a = run_gpu(R, scene, cams, fovs, params)
