@@ -199,9 +199,14 @@ int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fove
  * key (Sec. 3: the instances are sorted).  Equal keys keep their input order,
  * so instances written in Gaussian order come out ordered by (key, gid).
  * Sorts min(*n_dev, capacity) pairs in place; `ws` must hold
- * vrs_sort_pairs_workspace_size(capacity) bytes. */
+ * vrs_sort_pairs_workspace_size(capacity) bytes.  Each 8-bit digit pass is
+ * reduce-then-scan (per-block digit counts, a multi-block scan, a stable
+ * scatter); no block waits on another.  status_dev (may be null) is the
+ * device status word of the other entry points; the sort itself reports no
+ * device-side condition. */
 int vrs_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity,
-                   int32_t key_bits, void* ws, size_t ws_bytes, vrs_stream_t stream);
+                   int32_t key_bits, void* ws, size_t ws_bytes, int32_t* status_dev,
+                   vrs_stream_t stream);
 size_t vrs_sort_pairs_workspace_size(size_t capacity);
 
 /* Tile ranges of sorted keys: ranges[t] = {first, last + 1} of global tile t,

@@ -80,7 +80,7 @@ SIGNATURES = {
     "vrs_duplicate": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
                            ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _S,
                            _P, _P, _S, _P, _P]),
-    "vrs_sort_pairs": (_I, [_P, _P, _P, _S, _I, _P, _S, _P]),
+    "vrs_sort_pairs": (_I, [_P, _P, _P, _S, _I, _P, _S, _P, _P]),
     "vrs_sort_pairs_workspace_size": (_S, [_S]),
     "vrs_tile_ranges": (_I, [_P, _P, _S, _U, _P, _P]),
     "vrs_sort": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),

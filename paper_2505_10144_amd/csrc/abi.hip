@@ -14,8 +14,8 @@ int launch_preprocess(const GaussPtrs&, const GeoViews&, const Knobs&, float*, u
 int launch_duplicate(const GaussPtrs&, const GeoViews&, const Knobs&, const float*, const uint32_t*, uint64_t*,
                      uint32_t*, size_t, uint32_t*, void*, int*, hipStream_t);
 size_t sort_ws_bytes(size_t capacity);
-int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, hipStream_t);
-int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*, bool, size_t, int, void*,
+int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, int*, hipStream_t);
+int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*, bool, size_t, int, void*, int*,
                          hipStream_t);
 
 // Bytes per Gaussian and view in `proj`: the FP32 render record plus the FP64
@@ -31,7 +31,7 @@ bool window_supported(int w);
 size_t order_ws_bytes(size_t items_max);
 const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, const uint32_t* count_dev,
                                    size_t items_max, const uint32_t* ranges, const RenderViews& views, void* ws,
-                                   hipStream_t s);
+                                   int* err, hipStream_t s);
 
 int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, void* plan, size_t items_max, hipStream_t s);
 }  // namespace vrs
@@ -318,13 +318,14 @@ int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fove
 size_t vrs_sort_pairs_workspace_size(size_t capacity) { return sort_ws_bytes(capacity); }
 
 int vrs_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity, int32_t key_bits,
-                   void* ws, size_t ws_bytes, vrs_stream_t stream) {
+                   void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream) {
     if (key_bits < 0 || key_bits > 64 || !n_dev) return VRS_ERR_INVALID_ARG;
     if (capacity > 0xFFFFFFFFull) return VRS_ERR_UNSUPPORTED;
     if (capacity > 0 && (!keys || !vals || !ws || ws_bytes < sort_ws_bytes(capacity) || !aligned(keys, 8) ||
                          !aligned(ws, 16)))
         return VRS_ERR_INVALID_ARG;
-    return launch_sort_pairs(keys, vals, n_dev, capacity, key_bits, ws, reinterpret_cast<hipStream_t>(stream));
+    return launch_sort_pairs(keys, vals, n_dev, capacity, key_bits, ws, status_dev,
+                             reinterpret_cast<hipStream_t>(stream));
 }
 
 int vrs_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity, uint32_t tiles_total,
@@ -349,7 +350,7 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
     if (capacity > 0) {
         // The first pass drops the dead keys of culled candidates.
         rc = launch_sort_pairs_ex(keys, gids, n_inst_dev, n_inst_dev + 1, true, capacity,
-                                  key_bits_for(L.tiles_total), ws, s);
+                                  key_bits_for(L.tiles_total), ws, status_dev, s);
         if (rc != VRS_OK) return rc;
     }
     return launch_tile_ranges(keys, n_inst_dev + 1, capacity, L.tiles_total, ranges, s);
@@ -425,7 +426,8 @@ int vrs_blend(const void* proj, int32_t n, const uint32_t* gids, const uint32_t*
     if (n_items == 0) return VRS_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const uint32_t* items = launch_order_items(plan_items(plan), n_items, static_cast<const uint32_t*>(plan),
-                                               L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off, s);
+                                               L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off,
+                                               status_dev, s);
     if (!items) return VRS_ERR_HIP;
     return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items,
                         order_counter(static_cast<char*>(ws) + L.order_off), p->blend_batch, p->schedule, R, knobs(p),
@@ -444,7 +446,8 @@ int vrs_blend_stats(const void* proj, int32_t n, const uint32_t* gids, const uin
     if (n_items == 0) return VRS_OK;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const uint32_t* items = launch_order_items(plan_items(plan), n_items, static_cast<const uint32_t*>(plan),
-                                               L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off, s);
+                                               L.items_max, ranges, R, static_cast<char*>(ws) + L.order_off,
+                                               nullptr, s);
     if (!items) return VRS_ERR_HIP;
     return launch_blend(static_cast<const float*>(proj), uint32_t(n), gids, ranges, items, n_items,
                         order_counter(static_cast<char*>(ws) + L.order_off), p->blend_batch, p->schedule, R, knobs(p),

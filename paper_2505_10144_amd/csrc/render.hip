@@ -25,7 +25,7 @@
 namespace vrs {
 
 size_t sort_ws_bytes(size_t capacity);
-int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, hipStream_t);
+int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, int*, hipStream_t);
 int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 
 constexpr int kRenderThreads = 256;
@@ -521,7 +521,7 @@ uint32_t* order_counter(void* ws) { return static_cast<uint32_t*>(ws); }
 // Writes the ordered items into the ordering area `ws` and returns them.
 const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, const uint32_t* count_dev,
                                    size_t items_max, const uint32_t* ranges, const RenderViews& views, void* ws,
-                                   hipStream_t s) {
+                                   int* err, hipStream_t s) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     char* base = static_cast<char*>(ws) + 256;
     uint64_t* keys = reinterpret_cast<uint64_t*>(base);
@@ -529,7 +529,7 @@ const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, cons
     void* sws = base + al(items_max * 8) + al(items_max * 4);
     hipLaunchKernelGGL(k_item_keys, dim3((n_items + 255) / 256), dim3(256), 0, s, items, n_items, ranges, views,
                        keys, vals);
-    if (launch_sort_pairs(keys, vals, count_dev, n_items, 8, sws, s) != VRS_OK) return nullptr;
+    if (launch_sort_pairs(keys, vals, count_dev, n_items, 8, sws, err, s) != VRS_OK) return nullptr;
     return vals;
 }
 

@@ -274,7 +274,8 @@ int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
 // Sort min(*n_first, capacity) pairs; with drop_first the first pass drops
 // dead keys and the remaining passes sort min(*n_rest, capacity) pairs.
 int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first, const uint32_t* n_rest,
-                         bool drop_first, size_t capacity, int key_bits, void* ws, hipStream_t s) {
+                         bool drop_first, size_t capacity, int key_bits, void* ws, int* err, hipStream_t s) {
+    (void)err;  // no pass waits on another block, so nothing can time out
     if (capacity == 0 || key_bits <= 0) return VRS_OK;
     const int nb = int(sort_blocks(capacity));
     uint64_t* k2 = static_cast<uint64_t*>(ws);
@@ -309,8 +310,8 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
 }
 
 int launch_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity, int key_bits,
-                      void* ws, hipStream_t s) {
-    return launch_sort_pairs_ex(keys, vals, n_dev, n_dev, false, capacity, key_bits, ws, s);
+                      void* ws, int* err, hipStream_t s) {
+    return launch_sort_pairs_ex(keys, vals, n_dev, n_dev, false, capacity, key_bits, ws, err, s);
 }
 
 int launch_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity, uint32_t tiles_total,

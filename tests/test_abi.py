@@ -114,8 +114,8 @@ def test_entry_points_validate_before_device_work():
     assert lib.vrs_preprocess(ctypes.byref(g), cam, fov, 1, ctypes.byref(p), null, null, null, null) == L.VRS_ERR_INVALID_ARG
     g.sh_degree = 3  # valid degree but NULL parameter pointers
     assert lib.vrs_preprocess(ctypes.byref(g), cam, fov, 1, ctypes.byref(p), null, null, null, null) == L.VRS_ERR_INVALID_ARG
-    assert lib.vrs_sort_pairs(null, null, null, 10, 40, null, 0, null) == L.VRS_ERR_INVALID_ARG
-    assert lib.vrs_sort_pairs(null, null, null, 10, 65, null, 0, null) == L.VRS_ERR_INVALID_ARG
+    assert lib.vrs_sort_pairs(null, null, null, 10, 40, null, 0, null, null) == L.VRS_ERR_INVALID_ARG
+    assert lib.vrs_sort_pairs(null, null, null, 10, 65, null, 0, null, null) == L.VRS_ERR_INVALID_ARG
     assert lib.vrs_fovea_plan(cam, fov, 1, ctypes.byref(p), null, 0, None, null) == L.VRS_ERR_INVALID_ARG
     imgs = (ctypes.c_void_p * 1)(0)
     assert lib.vrs_render_foveated(null, -1, null, null, cam, fov, 1, ctypes.byref(p), null, 0, imgs, null, 0,

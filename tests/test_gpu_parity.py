@@ -285,11 +285,13 @@ def test_sort_pairs_bit_exact_on_gpu_keys(R):
     n = int(r.n_inst[0].item())
     k0 = r.keys[:n].cpu().numpy().view(np.uint64).copy()
     v0 = r.gids[:n].cpu().numpy().view(np.uint32).copy()
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
     L.call("vrs_sort_pairs", ctypes.c_void_p(r.keys.data_ptr()), ctypes.c_void_p(r.gids.data_ptr()),
            ctypes.c_void_p(r.n_inst.data_ptr()), ctypes.c_size_t(r.capacity), r.key_bits(),
            ctypes.c_void_p(r.sort_ws.data_ptr()), ctypes.c_size_t(r.sort_ws.numel()),
-           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+           ctypes.c_void_p(st.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
+    assert int(st.item()) == 0
     ks = r.keys[:n].cpu().numpy().view(np.uint64)
     vs = r.gids[:n].cpu().numpy().view(np.uint32)
     order = np.argsort(k0, kind="stable")
@@ -309,7 +311,8 @@ def test_sort_pairs_bit_exact_on_gpu_keys(R):
 
 
 @pytest.mark.parametrize("n,bits,dups", [(0, 40, 1), (1, 40, 1), (4095, 64, 1), (4097, 33, 7),
-                                         (100_003, 46, 50), (300_000, 64, 1000)])
+                                         (100_003, 46, 50), (300_000, 64, 1000), (3_000_001, 64, 3),
+                                         (2_500_000, 8, 1)])
 def test_sort_pairs_random(R, n, bits, dups):
     from paper_2505_10144_amd import _lib as L
     import ctypes
@@ -327,10 +330,13 @@ def test_sort_pairs_random(R, n, bits, dups):
         vt[:n] = torch.from_numpy(vals.view(np.int32)).cuda()
     nt = torch.tensor([n], dtype=torch.int32, device="cuda")
     ws = torch.empty(int(L.load().vrs_sort_pairs_workspace_size(cap)), dtype=torch.uint8, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
     L.call("vrs_sort_pairs", ctypes.c_void_p(kt.data_ptr()), ctypes.c_void_p(vt.data_ptr()),
            ctypes.c_void_p(nt.data_ptr()), ctypes.c_size_t(cap), bits, ctypes.c_void_p(ws.data_ptr()),
-           ctypes.c_size_t(ws.numel()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+           ctypes.c_size_t(ws.numel()), ctypes.c_void_p(st.data_ptr()),
+           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
+    assert int(st.item()) == 0
     ks = kt[:n].cpu().numpy().view(np.uint64)
     vs = vt[:n].cpu().numpy().view(np.uint32)
     order = np.argsort(keys, kind="stable")
@@ -388,3 +394,38 @@ def test_stereo_full_size_sampled_tiles(R):
     sel = {v: sorted(set(rng.choice(grid.n, 6, replace=False).tolist() + [centre, centre + 1])) for v in range(2)}
     ref = oracle.render(scene, cams, fovs, params, OracleOptions(tiles=sel, workers=8))
     compare(imgs, ref, max_flag_frac=0.25)
+
+
+@pytest.mark.parametrize("frame", [0, 29])
+def test_unpruned_yaw_arc_sampled_tiles(R, frame):
+    """The unpruned-density workload (3M smaller, fainter Gaussians, stereo
+    foveated at 2064x2208) at the two ends of its +-20 degree head-yaw arc,
+    checked against the oracle on sampled tiles plus the fovea."""
+    scene, cams, fovs, params = synth.config_unpruned(0, frame=frame)
+    r, g, imgs = run_gpu(R, scene, cams, fovs, params)
+    rng = np.random.default_rng(100 + frame)
+    grid = otiles.TileGrid(cams[0].width, cams[0].height, 32)
+    centre = (grid.nty // 2) * grid.ntx + grid.ntx // 2
+    sel = {v: sorted(set(rng.choice(grid.n, 5, replace=False).tolist() + [centre])) for v in range(2)}
+    ref = oracle.render(scene, cams, fovs, params, OracleOptions(tiles=sel, workers=8))
+    compare(imgs, ref, max_flag_frac=0.25)
+
+
+def test_unpruned_yaw_arc_all_frames_run(R):
+    """Every frame of the 30-frame yaw arc renders through one renderer per
+    frame with finite output, no capacity error and alpha in [0, 1]."""
+    scene, cams, fovs, params = synth.config_unpruned(0, frame=0)
+    g = R.upload(scene)
+    for frame in range(0, 30, 3):
+        _, cams, fovs, params = synth.config_unpruned(0, frame=frame, n=16)  # cameras only
+        r = R.Renderer(cams, fovs, params, scene.n)
+        r.ensure_capacity(g)
+        imgs = r.render(g)
+        torch.cuda.synchronize()
+        kept = r.check()
+        assert kept > 0
+        for im in imgs:
+            assert bool(torch.isfinite(im).all())
+            a = im[3]
+            assert float(a.min()) >= 0.0 and float(a.max()) <= 1.0
+        print(f"[yaw] frame {frame} instances {kept}", flush=True)
