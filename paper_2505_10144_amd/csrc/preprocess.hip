@@ -146,14 +146,15 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave per block owns 64 consecutive (view, Gaussian) slots.  It first
-// copies their 64 tile-test records into LDS with coalesced loads, then deals
-// the slots' candidates out to its lanes 64 at a time, so every lane tests
-// one candidate per step whatever the spread of per-Gaussian counts.  The
-// owner of candidate j of the wave is found by a 6-step search of the wave's
-// count prefix in LDS.  n_inst[0]: candidates (from the scan), n_inst[1]:
-// kept instances.
-constexpr int kTgWords = int(sizeof(TileGeo) / 16);  // 16-byte words per record
+// One wave per block owns 64 consecutive (view, Gaussian) slots and deals
+// their candidates out to its lanes 64 at a time, so every lane tests one
+// candidate per step whatever the spread of per-Gaussian counts.  The owner
+// of candidate j of the wave is found by a 6-step search of the wave's count
+// prefix in LDS; the lane then reads the owner's tile-test record directly
+// (the block's 64 records are one contiguous 14 KB span that stays in the
+// caches), which keeps LDS small enough for four waves per SIMD on the
+// latency-bound FP64 test.  n_inst[0]: candidates (from the scan),
+// n_inst[1]: kept instances.
 
 __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const TileGeo* __restrict__ tgeo,
                                                   const uint32_t* __restrict__ offsets,
@@ -161,25 +162,15 @@ __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const T
                                                   uint32_t* __restrict__ n_inst, uint64_t* __restrict__ keys,
                                                   uint32_t* __restrict__ gids, size_t capacity) {
     __shared__ uint32_t pre[65];
-    __shared__ TileGeo geo[64];
     __shared__ GeoView vw[VRS_MAX_VIEWS];
     const int lane = threadIdx.x;
     const size_t s0 = size_t(blockIdx.x) * 64;
     const size_t nown = min(size_t(64), nslots - s0);
-    // The views this block's slots belong to, copied to LDS with uniform
-    // (scalar) reads of the argument table, so lanes of different views
-    // read their constants from LDS.
     const int v_lo = int(s0 / size_t(n)), v_hi = int((s0 + nown - 1) / size_t(n));
     for (int v = v_lo; v <= v_hi; ++v)
         if (lane == 0) vw[v] = views.v[v];
     const size_t s = s0 + lane;
     const uint32_t c = s < nslots ? counts[s] : 0u;
-    // Coalesced copy of the block's records: word w of the block's span.
-    {
-        const int4* src = reinterpret_cast<const int4*>(tgeo + s0);
-        int4* dst = reinterpret_cast<int4*>(geo);
-        for (int w = lane; w < int(nown) * kTgWords; w += 64) dst[w] = src[w];
-    }
     uint32_t incl = c;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -207,7 +198,7 @@ __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const T
             const int v = int(o / size_t(n));
             const int i = int(o - size_t(v) * size_t(n));
             const GeoView& V = vw[v];
-            const TileGeo& tg = geo[ow];
+            const TileGeo tg = tgeo[o];
             const int k = int(j - pre[ow]);
             const int tx = tg.tx0 + k % tg.ncx, ty = tg.ty0 + k / tg.ncx;
             double bx0, by0, bx1, by1, depth;

@@ -388,10 +388,21 @@ k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __res
 
 // K7: LOW pixels of a foveated view take the 3x3 binomial blur of the
 // nearest-neighbour-upsampled image (coordinates clamped to the image); other
-// pixels are copied.
-__global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __restrict__ cls) {
-    const int x = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+// pixels are copied.  One block per 64x4 tile (a wave reads whole 256-byte
+// row segments of each plane).  Workgroups are dealt to the
+// eight XCDs round-robin, and each XCD has its own L2; the block index is
+// remapped so that every XCD gets a contiguous band of tile rows, whose
+// blur halos then hit in that XCD's L2 instead of being fetched again by a
+// neighbour XCD.
+constexpr uint32_t kXcds = 8;
+
+__global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __restrict__ cls, uint32_t ntiles,
+                                                 uint32_t per_xcd) {
+    const uint32_t tid = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (tid >= ntiles) return;
+    const uint32_t ntx = uint32_t(V.W + 63) / 64;
+    const int x = int(tid % ntx) * 64 + int(threadIdx.x & 63);
+    const int y = int(tid / ntx) * 4 + int(threadIdx.x >> 6);
     if (x >= V.W || y >= V.H) return;
     const size_t plane = size_t(V.W) * size_t(V.H);
     const uint8_t c = cls[V.cls_off + size_t(y >> 4) * V.ntx16 + (x >> 4)];
@@ -537,7 +548,9 @@ int launch_compose(const RenderViews& views, const uint8_t* cls, hipStream_t s) 
     for (int v = 0; v < views.n; ++v) {
         const RenderView& V = views.v[v];
         if (!V.foveated) continue;
-        hipLaunchKernelGGL(k_compose, dim3((V.W + 15) / 16, (V.H + 15) / 16), dim3(256), 0, s, V, cls);
+        const uint32_t ntiles = uint32_t((V.W + 63) / 64) * uint32_t((V.H + 3) / 4);
+        const uint32_t per = (ntiles + kXcds - 1) / kXcds;
+        hipLaunchKernelGGL(k_compose, dim3(per * kXcds), dim3(256), 0, s, V, cls, ntiles, per);
     }
     return launch_status(hipGetLastError());
 }
