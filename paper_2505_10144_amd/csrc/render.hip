@@ -221,7 +221,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
                     const uint32_t gid = gids[b0 + lane];
                     const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
                     const float4 p7 = rec[7];
-                    rel = !(p7.z < rx0 || p7.x > rx1 || p7.w < ry0 || p7.y > ry1);
+                    rel = (p7.z >= rx0) & (p7.x <= rx1) & (p7.w >= ry0) & (p7.y <= ry1);
                     if (rel) {
                         const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
                         const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];

@@ -2,15 +2,19 @@
 // digits, K5: per-tile [start, end) ranges of the sorted keys, and the
 // exclusive scan shared with the instantiation stage.
 //
-// Each pass is reduce-then-scan: (1) every block counts the digits of its
-// 4096-key tile in LDS, (2) a three-phase multi-block scan of the digit-major
-// [256][blocks] histogram gives every (digit, block) its output offset, (3)
-// every block ranks its keys stably -- each wave owns a contiguous 1024-key
-// slice, ranks within a 64-key step by matching digits with ballots, and the
-// per-wave digit counts are prefix-summed across waves -- and scatters them.
-// No inter-block waiting, so passes are deterministic and need no
-// forward-progress assumptions.  Pair counts are read on the device, so the
-// grid covers `capacity` and surplus blocks only contribute zero counts.
+// Two kernels first count the digits of every pass at once (the digit
+// totals do not depend on the order of the keys).  Each pass is then
+// reduce-then-scan: (1) every block counts the digits of its 4096-key tile
+// in LDS, (2) one block per digit scans that digit's row of the digit-major
+// [256][blocks] histogram and adds the totals of the smaller digits, giving
+// every (digit, block) its output offset,
+// (3) every block ranks its keys stably -- each wave owns a contiguous
+// 1024-key slice, ranks within a 64-key step by matching digits with
+// ballots, and the per-wave digit counts are prefix-summed across waves --
+// and scatters them.  No inter-block waiting, so passes are deterministic
+// and need no forward-progress assumptions.  Pair counts are read on the
+// device, so the grid covers `capacity` and surplus blocks only contribute
+// zero counts.
 //
 // The first pass can drop dead keys (all ones): instantiation writes one for
 // every candidate tile that fails the tile test, and they never reach the
@@ -25,6 +29,7 @@ constexpr int kSortItemsPerLane = 16;
 constexpr int kSortTile = kSortThreads * kSortItemsPerLane;  // 4096
 constexpr int kRadix = 256;
 constexpr uint64_t kDeadKey = ~0ull;
+constexpr int kMaxPasses = 8;
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of uint32 (per-block scan, scan of block sums, add-back).
@@ -157,12 +162,19 @@ __device__ inline uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Rank the block's keys stably, place them in LDS in (digit, rank) order,
+// then write each digit's run to its global offset: consecutive threads
+// write consecutive addresses within a run.
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, size_t capacity, int shift, int drop,
     const uint32_t* __restrict__ hist, int nblocks) {
     __shared__ uint32_t wcnt[kSortWaves][kRadix];
-    __shared__ uint32_t goff[kRadix];
+    __shared__ uint32_t goff[kRadix];     // global offset of each digit's run
+    __shared__ uint32_t loff[kRadix];     // start of each digit's run in the block
+    __shared__ uint32_t scan_sh[kSortThreads];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int lane = t & 63;
@@ -205,24 +217,99 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
-    // Exclusive prefix over waves for every digit (thread t owns digit t).
-    {
-        uint32_t acc = 0;
-        for (int k = 0; k < kSortWaves; ++k) {
-            const uint32_t c = wcnt[k][t];
-            wcnt[k][t] = acc;
-            acc += c;
-        }
+    // Exclusive prefix over waves for every digit (thread t owns digit t),
+    // then over digits: the start of each digit's run in the block.
+    uint32_t cnt = 0;
+    for (int k = 0; k < kSortWaves; ++k) {
+        const uint32_t c = wcnt[k][t];
+        wcnt[k][t] = cnt;
+        cnt += c;
     }
+    uint32_t live_total;
+    loff[t] = block_exclusive_scan(cnt, scan_sh, live_total);
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kSortItemsPerLane; ++it) {
         if (live[it]) {
             const uint32_t d = uint32_t(key[it] >> shift) & 0xFFu;
-            const size_t pos = size_t(goff[d]) + wcnt[w][d] + rank[it];
-            kout[pos] = key[it];
-            vout[pos] = val[it];
+            const uint32_t lp = loff[d] + wcnt[w][d] + rank[it];
+            skey[lp] = key[it];
+            sval[lp] = val[it];
         }
+    }
+    __syncthreads();
+    for (uint32_t i = uint32_t(t); i < live_total; i += kSortThreads) {
+        const uint64_t k = skey[i];
+        const uint32_t d = uint32_t(k >> shift) & 0xFFu;
+        const size_t pos = size_t(goff[d]) + (i - loff[d]);
+        kout[pos] = k;
+        vout[pos] = sval[i];
+    }
+}
+
+// Digit counts of every pass for one 4096-key tile: block b writes
+// counts[p][b][d].
+__global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* __restrict__ keys,
+                                                               const uint32_t* __restrict__ n_dev, size_t capacity,
+                                                               int passes, int drop,
+                                                               uint32_t* __restrict__ counts, int nblocks) {
+    __shared__ uint32_t cnt[kMaxPasses][kRadix];
+    for (int p = 0; p < kMaxPasses; ++p) cnt[p][threadIdx.x] = 0;
+    __syncthreads();
+    const size_t n = n_eff(n_dev, capacity);
+    const size_t base = size_t(blockIdx.x) * kSortTile;
+    for (int k = 0; k < kSortItemsPerLane; ++k) {
+        const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
+        if (idx < n) {
+            const uint64_t key = keys[idx];
+            if (!(drop && key == kDeadKey))
+                for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][uint32_t(key >> (8 * p)) & 0xFFu], 1u);
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < passes; ++p)
+        counts[(size_t(p) * nblocks + blockIdx.x) * kRadix + threadIdx.x] = cnt[p][threadIdx.x];
+}
+
+// Digit totals of every pass: block (p, g) sums digits 4g .. 4g+3 of pass p
+// over all tiles, 64 threads per digit.
+__global__ void __launch_bounds__(256) k_digit_totals(const uint32_t* __restrict__ counts, int nblocks,
+                                                      uint32_t* __restrict__ totals) {
+    const int p = blockIdx.y, d = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const uint32_t* c = counts + size_t(p) * nblocks * kRadix + d;
+    uint32_t tot = 0;
+    for (int b = lane; b < nblocks; b += 64) tot += c[size_t(b) * kRadix];
+    for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off);
+    if (lane == 0) totals[p * kRadix + d] = tot;
+}
+
+// One block per digit d: exclusive scan of the digit's per-block counts,
+// plus the digit's offset (the totals of the smaller digits), in place.
+__global__ void __launch_bounds__(kScanThreads) k_digit_row_scan(uint32_t* __restrict__ hist, int nblocks,
+                                                                 const uint32_t* __restrict__ totals) {
+    __shared__ uint32_t sh[kScanThreads];
+    const int d = blockIdx.x;
+    uint32_t tot;
+    block_exclusive_scan(int(threadIdx.x) < d ? totals[threadIdx.x] : 0u, sh, tot);
+    uint32_t carry = tot;  // sum of the totals of digits < d
+    uint32_t* row = hist + size_t(d) * nblocks;
+    for (int c0 = 0; c0 < nblocks; c0 += kScanTile) {
+        const int base = c0 + int(threadIdx.x) * kScanItems;
+        uint32_t v[kScanItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < nblocks ? row[base + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t t2;
+        uint32_t ex = block_exclusive_scan(sum, sh, t2) + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < nblocks) row[base + k] = ex;
+            ex += v[k];
+        }
+        carry += t2;
     }
 }
 
@@ -255,12 +342,15 @@ __global__ void k_tile_ranges(const uint64_t* __restrict__ keys, const uint32_t*
 // ---------------------------------------------------------------------------
 static size_t sort_blocks(size_t capacity) { return (capacity + kSortTile - 1) / kSortTile; }
 
+// Workspace: ping-pong pairs, the [256][blocks] histogram of one pass, the
+// digit offsets of every pass, and the per-tile digit counts of every pass.
 size_t sort_ws_bytes(size_t capacity) {
     const size_t nb = sort_blocks(capacity) ? sort_blocks(capacity) : 1;
     size_t b = capacity * (sizeof(uint64_t) + sizeof(uint32_t));  // ping-pong buffers
     b = (b + 255) & ~size_t(255);
-    const size_t hist = size_t(kRadix) * nb;
-    b += (hist + scan_tmp_words(hist) + 64) * sizeof(uint32_t);
+    b += ((size_t(kRadix) * nb + 63) & ~size_t(63)) * sizeof(uint32_t);
+    b += size_t(kMaxPasses) * kRadix * sizeof(uint32_t);
+    b += size_t(kMaxPasses) * nb * kRadix * sizeof(uint32_t);
     return b;
 }
 
@@ -284,8 +374,14 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
     off = (off + 255) & ~size_t(255);
     uint32_t* hist = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + off);
     const size_t hist_len = size_t(kRadix) * nb;
-    uint32_t* tmp = hist + hist_len;
+    uint32_t* totals = hist + ((hist_len + 63) & ~size_t(63));
+    uint32_t* counts = totals + size_t(kMaxPasses) * kRadix;
     const int passes = (key_bits + 7) / 8;
+    // Digit totals of every pass (the live keys are the same in every pass;
+    // the first pass drops the dead ones).
+    hipLaunchKernelGGL(k_digit_counts, dim3(nb), dim3(kSortThreads), 0, s, keys, n_first, capacity, passes,
+                       drop_first ? 1 : 0, counts, nb);
+    hipLaunchKernelGGL(k_digit_totals, dim3(kRadix / 4, passes), dim3(256), 0, s, counts, nb, totals);
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     for (int p = 0; p < passes; ++p) {
@@ -294,8 +390,7 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
         const uint32_t* n_dev = (p == 0 || !drop_first) ? n_first : n_rest;
         hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n_dev, capacity, shift, drop, hist,
                            nb);
-        int rc = launch_exclusive_scan(hist, hist, hist_len, nullptr, tmp, s);
-        if (rc != VRS_OK) return rc;
+        hipLaunchKernelGGL(k_digit_row_scan, dim3(kRadix), dim3(kScanThreads), 0, s, hist, nb, totals + p * kRadix);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, va, kb, vb, n_dev, capacity,
                            shift, drop, hist, nb);
         uint64_t* tk = ka; ka = kb; kb = tk;
