@@ -169,6 +169,35 @@ __device__ inline bool make_geo(const GaussLocal& G, const GeoView& V, const Kno
 // the x' range, likewise for y.  The whole grid when the cone comes within
 // 0.1 degree of the plane z = 0.  Only square roots: cos/sin of beta follow
 // from tan(beta).
+//
+// The box is then intersected with the bounding box of the exact footprint:
+// alpha >= alpha_min at pixel offset d from the mean's image point iff
+// |M d|^2 <= kappa h^2 with h = 1 + a3 . d > 0, i.e. inside the conic
+//   d^T (M^T M - kappa a3 a3^T) d - 2 kappa a3 . d - kappa <= 0.
+// When its matrix A is positive definite the conic is an ellipse with
+// centre kappa A^-1 a3 and "radius" r^2 = kappa^2 a3^T A^-1 a3 + kappa, whose
+// half-extents along x and y are r sqrt((A^-1)_00) and r sqrt((A^-1)_11).
+// Elongated splats get much tighter boxes than the cone's.
+__device__ inline bool conic_box(const TileGeo& t, double& xlo, double& xhi, double& ylo, double& yhi) {
+    const double k = fmax(t.kappa, 0.0);
+    const double* M = t.M;
+    const double A00 = M[0] * M[0] + M[2] * M[2] - k * t.a3x * t.a3x;
+    const double A01 = M[0] * M[1] + M[2] * M[3] - k * t.a3x * t.a3y;
+    const double A11 = M[1] * M[1] + M[3] * M[3] - k * t.a3y * t.a3y;
+    const double det = A00 * A11 - A01 * A01;
+    // Positive definite and not close to singular (the box's rounding error
+    // grows with A's condition number; near-parabolic footprints keep the
+    // cone's box).
+    if (!(A00 > 0.0 && det > 1e-9 * A00 * A11)) return false;
+    const double i00 = A11 / det, i01 = -A01 / det, i11 = A00 / det;
+    const double ax = i00 * t.a3x + i01 * t.a3y, ay = i01 * t.a3x + i11 * t.a3y;  // A^-1 a3
+    const double r2 = k * k * (t.a3x * ax + t.a3y * ay) + k;
+    const double hx = sqrt(r2 * i00), hy = sqrt(r2 * i11);
+    const double cx = t.x0 + k * ax, cy = t.y0 + k * ay;
+    xlo = cx - hx; xhi = cx + hx; ylo = cy - hy; yhi = cy + hy;
+    return isfinite(xlo) && isfinite(xhi) && isfinite(ylo) && isfinite(yhi);
+}
+
 __device__ inline void cone_tiles(const Geo& g, const GeoView& V, int& tx0, int& tx1, int& ty0, int& ty1,
                                   float bbox[4]) {
     const double rq = sqrt(fmax(g.tg.kappa, 0.0) * g.lam_max);
@@ -176,20 +205,30 @@ __device__ inline void cone_tiles(const Geo& g, const GeoView& V, int& tx0, int&
     const double sb = rq / hyp, cb = V.f / hyp;
     const double uz = g.u[2];
     const double st = sqrt(fmax(1.0 - uz * uz, 0.0));
-    // cos(theta_u + beta) <= cos(89.9 deg)
-    if (uz * cb - st * sb <= 1.7453283658983088e-3) {
+    const double m = 0.5;  // pixels of margin against rounding
+    double pxlo = -INFINITY, pxhi = INFINITY, pylo = -INFINITY, pyhi = INFINITY;
+    // cos(theta_u + beta) > cos(89.9 deg): the cone's image is bounded.
+    if (uz * cb - st * sb > 1.7453283658983088e-3) {
+        const double inv_a = 1.0 / (uz * uz - sb * sb);
+        const double dx = sqrt(fmax(g.u[0] * g.u[0] + uz * uz - sb * sb, 0.0));
+        const double dy = sqrt(fmax(g.u[1] * g.u[1] + uz * uz - sb * sb, 0.0));
+        pxlo = double(V.cx) + V.f * (g.u[0] * uz - sb * dx) * inv_a - m;
+        pxhi = double(V.cx) + V.f * (g.u[0] * uz + sb * dx) * inv_a + m;
+        pylo = double(V.cy) + V.f * (g.u[1] * uz - sb * dy) * inv_a - m;
+        pyhi = double(V.cy) + V.f * (g.u[1] * uz + sb * dy) * inv_a + m;
+    }
+    double exlo, exhi, eylo, eyhi;
+    if (conic_box(g.tg, exlo, exhi, eylo, eyhi)) {
+        pxlo = fmax(pxlo, exlo - m);
+        pxhi = fmin(pxhi, exhi + m);
+        pylo = fmax(pylo, eylo - m);
+        pyhi = fmin(pyhi, eyhi + m);
+    }
+    if (!(isfinite(pxlo) && isfinite(pxhi) && isfinite(pylo) && isfinite(pyhi))) {
         tx0 = 0; ty0 = 0; tx1 = V.ntx - 1; ty1 = V.nty - 1;
         bbox[0] = -INFINITY; bbox[1] = -INFINITY; bbox[2] = INFINITY; bbox[3] = INFINITY;
         return;
     }
-    const double inv_a = 1.0 / (uz * uz - sb * sb);
-    const double dx = sqrt(fmax(g.u[0] * g.u[0] + uz * uz - sb * sb, 0.0));
-    const double dy = sqrt(fmax(g.u[1] * g.u[1] + uz * uz - sb * sb, 0.0));
-    const double m = 0.5;  // pixels of margin against rounding
-    const double pxlo = double(V.cx) + V.f * (g.u[0] * uz - sb * dx) * inv_a - m;
-    const double pxhi = double(V.cx) + V.f * (g.u[0] * uz + sb * dx) * inv_a + m;
-    const double pylo = double(V.cy) + V.f * (g.u[1] * uz - sb * dy) * inv_a - m;
-    const double pyhi = double(V.cy) + V.f * (g.u[1] * uz + sb * dy) * inv_a + m;
     // Pixel box, rounded outwards to whole pixels.
     bbox[0] = float(floor(pxlo));
     bbox[1] = float(floor(pylo));

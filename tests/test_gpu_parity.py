@@ -382,6 +382,36 @@ def test_record_colours_and_alpha(R):
         np.testing.assert_allclose(np.exp2(rec[v, ok, 10]), pre["sigma"][ok], rtol=1e-6)
 
 
+@pytest.mark.parametrize("scale", [(-3.5, 1.2), (-2.5, 0.5)])
+def test_record_boxes_contain_the_footprint(R, scale):
+    """K1's pixel box (cone bound intersected with the exact conic footprint
+    box) contains every pixel centre where the oracle's alpha reaches
+    alpha_min, for anisotropic splats near and far, including ones that
+    cross the image border and ones close to the camera."""
+    from oracle.render import preprocess_view, _alpha_fn
+    from oracle import camera as ocam
+    scene = synth.uniform_scene(7, 300, lo=-1.5, hi=1.5, log_scale=scale)
+    cam = synth.camera_translate((0.0, 0.0, -2.2), 100.0, 96, 80)
+    params = synth.default_params(tile=16, window=8)
+    r, g = _stage_setup(R, scene, [cam], [synth.fovea_off()], params)
+    rec = r.records().cpu().numpy().astype(np.float64)[0]
+    pre = preprocess_view(scene, cam, params)
+    px, py = ocam.pixel_centers(0, 0, cam.width, cam.height)
+    rays = ocam.ray_dirs(cam, px, py)
+    checked = 0
+    for gi in np.nonzero(pre["valid"])[0]:
+        a, lnag = _alpha_fn(pre, gi, cam, rays, params)
+        hit = lnag >= np.log(np.float64(params.alpha_min)) + 1e-9
+        if not hit.any():
+            continue
+        x0b, y0b, x1b, y1b = rec[gi, 28:32]
+        inside = (px >= x0b) & (px <= x1b) & (py >= y0b) & (py <= y1b)
+        assert np.all(inside[hit]), (int(gi), rec[gi, 28:32], px[hit & ~inside][:3], py[hit & ~inside][:3])
+        checked += 1
+    print(f"[boxes] {checked} splats checked", flush=True)
+    assert checked > 50
+
+
 def test_stereo_full_size_sampled_tiles(R):
     """The full 500k-Gaussian stereo workload at 2064x2208 per eye, in the
     launch configuration of the benchmark, checked on sampled tiles (plus the
