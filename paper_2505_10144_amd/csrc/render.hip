@@ -30,22 +30,26 @@ int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 
 constexpr int kRenderThreads = 256;
 constexpr int kBatch = 64;      // entries staged per wave and batch
-constexpr int kStage = 7;       // float4 per staged entry
+constexpr int kStage = 6;       // float4 per staged entry
 constexpr int kInbox = 8;       // entries a lane collects before the wave drains
 
+// A window entry: depth, alpha and the Gaussian's index; its colour is
+// fetched from the render record when the entry is blended.
 struct Slot {
-    float t, a, r, g, b;
+    float t, a;
+    uint32_t id;
 };
 
 template <int W>
 struct Window {
-    float t[W], a[W], r[W], g[W], b[W];
+    float t[W], a[W];
+    uint32_t id[W];
 
     __device__ inline void init() {
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             t[i] = -FLT_MAX;  // placeholders: blending them is a no-op (alpha 0)
-            a[i] = 0.f; r[i] = 0.f; g[i] = 0.f; b[i] = 0.f;
+            a[i] = 0.f; id[i] = 0u;
         }
     }
 
@@ -65,22 +69,16 @@ struct Window {
         Slot e;
         e.t = c[0] ? t[0] : x.t;
         e.a = c[0] ? a[0] : x.a;
-        e.r = c[0] ? r[0] : x.r;
-        e.g = c[0] ? g[0] : x.g;
-        e.b = c[0] ? b[0] : x.b;
+        e.id = c[0] ? id[0] : x.id;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             t[i] = c[i] ? x.t : t[i];
             a[i] = c[i] ? x.a : a[i];
-            r[i] = c[i] ? x.r : r[i];
-            g[i] = c[i] ? x.g : g[i];
-            b[i] = c[i] ? x.b : b[i];
+            id[i] = c[i] ? x.id : id[i];
             if (i + 1 < W) {
                 t[i] = c[i + 1] ? t[i + 1] : t[i];
                 a[i] = c[i + 1] ? a[i + 1] : a[i];
-                r[i] = c[i + 1] ? r[i + 1] : r[i];
-                g[i] = c[i + 1] ? g[i + 1] : g[i];
-                b[i] = c[i + 1] ? b[i + 1] : b[i];
+                id[i] = c[i + 1] ? id[i + 1] : id[i];
             }
             // Keep each slot's update together so that it can be done in
             // the slot's own registers (no rotation copies at the loop edge).
@@ -94,21 +92,34 @@ struct Accum {
     float T, cr, cg, cb;
     bool alive;
 
-    // Front-to-back blending of one entry; the entry that would take T below
-    // t_min is not blended and stops the sample.  Branch-free so that the
-    // window state never merges across divergent paths.
-    __device__ inline void blend(float a, float r, float g, float b, float t_min) {
+    // Front-to-back blending of one entry, split in two: weight() takes the
+    // entry's alpha, advances the transmittance and returns the entry's
+    // weight T alpha (zero when it is not blended: the entry that would take
+    // T below t_min stops the sample); add() accumulates weight x colour.
+    // Colours are added in the order of the weights, so deferring add() does
+    // not change the result.  Branch-free so that the window state never
+    // merges across divergent paths.
+    __device__ inline float weight(float a, float t_min) {
         const float Tn = T * (1.f - a);
         const bool stop = Tn < t_min;
         const bool ok = alive && !stop;
         const float w = ok ? T * a : 0.f;
+        T = ok ? Tn : T;
+        alive = ok;
+        return w;
+    }
+    __device__ inline void add(float w, float r, float g, float b) {
         cr = fmaf(w, r, cr);
         cg = fmaf(w, g, cg);
         cb = fmaf(w, b, cb);
-        T = ok ? Tn : T;
-        alive = ok;
     }
 };
+
+// Colour of Gaussian `gid` in a view's render records (fields 25..27, the
+// y, z, w of the record's seventh float4).
+__device__ inline float4 record_colour(const float* __restrict__ vproj, uint32_t gid) {
+    return reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec)[6];
+}
 
 __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -136,7 +147,7 @@ __device__ inline void wave_sync_lds() {
 // instrumented variant inserts immediately (an inbox of one), so that its
 // counters measure the algorithm's work.
 template <int W, bool STATS>
-__device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], float4 (*ib)[64], float (*ibb)[64],
+__device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], float2 (*ib)[64], uint32_t (*ibg)[64],
                                    const float* __restrict__ proj, uint32_t n_gauss,
                                    const uint32_t* __restrict__ gids, const uint32_t* __restrict__ ranges,
                                    const RenderViews& views, const Knobs& kn, int batch,
@@ -184,6 +195,8 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     const float amax = kn.alpha_max, tmin = kn.t_min;
     uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0, n_push = 0;
     int cnt = 0;  // entries in this lane's inbox
+    float pw = 0.f;                                 // weight of the last emission
+    float4 pc = make_float4(0.f, 0.f, 0.f, 0.f);   // its colour (y, z, w)
 
     // This wave's samples lie in a pixel rectangle; list entries whose box
     // misses it cannot reach alpha_min at any of them and are skipped for
@@ -224,7 +237,8 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
                     rel = (p7.z >= rx0) & (p7.x <= rx1) & (p7.w >= ry0) & (p7.y <= ry1);
                     if (rel) {
                         const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
-                        const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
+                        const float4 p4 = rec[4], p5 = rec[5];
+                        const float wy2 = vproj[size_t(gid) * kRec + 24];
                         // Mean offset relative to the tile origin, split so that
                         // the integer part is exact: (ox - x0i) - x0f.
                         const float ex = float(ox - int(p0.x)) - p0.z;
@@ -234,8 +248,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
                         st[lane][2] = make_float4(p2.z, p2.w, p3.x, p3.y);      // l2s kap n0 nx
                         st[lane][3] = make_float4(p3.z, p4.x, p4.y, p4.z);      // ny w0
                         st[lane][4] = make_float4(p4.w, p5.x, p5.y, p5.z);      // wx wy.x
-                        st[lane][5] = make_float4(p5.w, p6.x, p6.y, p6.z);      // wy.yz r g
-                        st[lane][6] = make_float4(p6.w, 0.f, 0.f, 0.f);         // b
+                        st[lane][5] = make_float4(p5.w, wy2, __uint_as_float(gid), 0.f);  // wy.yz gid
                     }
                 }
                 todo = __ballot(rel);
@@ -259,7 +272,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
                 n_contrib += pass ? 1u : 0u;
             }
             if (pass) {
-                const float4 f3 = st[j][3], f4 = st[j][4], f5 = st[j][5], f6 = st[j][6];
+                const float4 f3 = st[j][3], f4 = st[j][4], f5 = st[j][5];
                 const float a = fminf(amax, exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2)));
                 const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
                 const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
@@ -267,8 +280,8 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
                 const float w2 = fmaf(f4.z, dx, fmaf(f5.y, dy, f3.w));
                 const float den = fmaf(w0, w0, fmaf(w1, w1, w2 * w2));
                 const float t = num * __builtin_amdgcn_rcpf(den);
-                ib[cnt][lane] = make_float4(t, a, f5.z, f5.w);
-                ibb[cnt][lane] = f6.x;
+                ib[cnt][lane] = make_float2(t, a);
+                ibg[cnt][lane] = __float_as_uint(f5.z);
                 ++cnt;
             }
             if (__ballot(cnt >= kCap) != 0ull) {  // wave-uniform
@@ -283,20 +296,35 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
             if (__ballot(has) == 0ull) break;  // wave-uniform
             if (STATS) ++n_push;
             Slot x;
-            x.t = -INFINITY; x.a = 0.f; x.r = 0.f; x.g = 0.f; x.b = 0.f;
+            x.t = -INFINITY; x.a = 0.f; x.id = 0u;
             if (has) {
-                const float4 v4 = ib[i][lane];
-                x.t = v4.x; x.a = v4.y; x.r = v4.z; x.g = v4.w; x.b = ibb[i][lane];
+                const float2 v2 = ib[i][lane];
+                x.t = v2.x; x.a = v2.y; x.id = ibg[i][lane];
             }
             const Slot e = win.push(x);
-            acc.blend(e.a, e.r, e.g, e.b, tmin);
+            const float w = acc.weight(e.a, tmin);
+            // Add the previous emission, whose colour load was issued one
+            // step earlier, then issue this one's.
+            acc.add(pw, pc.y, pc.z, pc.w);
+            pw = w;
+            pc = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (w != 0.f) pc = record_colour(vproj, e.id);
         }
         cnt = 0;
         if (!full || __ballot(acc.alive) == 0ull) break;
     }
-    // Flush the window in ascending depth order.
+    acc.add(pw, pc.y, pc.z, pc.w);
+    // Flush the window in ascending depth order: weights first (they chain
+    // through T), then the colours.
+    float wf[W];
 #pragma unroll
-    for (int i = 0; i < W; ++i) acc.blend(win.a[i], win.r[i], win.g[i], win.b[i], tmin);
+    for (int i = 0; i < W; ++i) wf[i] = acc.weight(win.a[i], tmin);
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (wf[i] != 0.f) c = record_colour(vproj, win.id[i]);
+        acc.add(wf[i], c.y, c.z, c.w);
+    }
 
     if (STATS) {
         // Wave sums, then one atomic per counter and wave (staged entries are
@@ -360,17 +388,17 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
 // ends.  The counter must be zero at launch; every wave exits after drawing
 // a unit past the end.
 template <int W, bool STATS, bool PERSIST>
-__global__ void __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(W <= 16 ? 2 : 1)))
+__global__ void __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(W <= 16 ? 3 : 1)))
 k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __restrict__ gids,
          const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ items, uint32_t n_items,
          uint32_t* __restrict__ counter, int batch, RenderViews views, Knobs kn,
          unsigned long long* __restrict__ stats) {
     __shared__ float4 stage[kRenderThreads / 64][kBatch][kStage];
-    __shared__ float4 inbox[kRenderThreads / 64][kInbox][64];
-    __shared__ float inbox_b[kRenderThreads / 64][kInbox][64];
+    __shared__ float2 inbox[kRenderThreads / 64][kInbox][64];
+    __shared__ uint32_t inbox_id[kRenderThreads / 64][kInbox][64];
     const int slot = int(threadIdx.x) >> 6;
     if (!PERSIST) {
-        render_unit<W, STATS>(items[blockIdx.x], slot, stage[slot], inbox[slot], inbox_b[slot], proj, n_gauss, gids,
+        render_unit<W, STATS>(items[blockIdx.x], slot, stage[slot], inbox[slot], inbox_id[slot], proj, n_gauss, gids,
                               ranges, views, kn, batch, stats);
         return;
     }
@@ -381,7 +409,7 @@ k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __res
         if (lane == 0) u = atomicAdd(counter, 1u);
         u = __shfl(u, 0);
         if (u >= n_units) break;
-        render_unit<W, STATS>(items[u >> 2], int(u & 3u), stage[slot], inbox[slot], inbox_b[slot], proj, n_gauss,
+        render_unit<W, STATS>(items[u >> 2], int(u & 3u), stage[slot], inbox[slot], inbox_id[slot], proj, n_gauss,
                               gids, ranges, views, kn, batch, stats);
     }
 }
