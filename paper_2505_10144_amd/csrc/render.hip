@@ -31,7 +31,7 @@ int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 constexpr int kRenderThreads = 256;
 constexpr int kBatch = 64;      // entries staged per wave and batch
 constexpr int kStage = 6;       // float4 per staged entry
-constexpr int kInbox = 8;       // entries a lane collects before the wave drains
+constexpr int kInbox = 5;       // entries a lane collects before the wave drains
 
 // A window entry: depth, alpha and the Gaussian's index; its colour is
 // fetched from the render record when the entry is blended.
@@ -315,15 +315,23 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     }
     acc.add(pw, pc.y, pc.z, pc.w);
     // Flush the window in ascending depth order: weights first (they chain
-    // through T), then the colours.
+    // through T), then the colours, four loads in flight at a time (which
+    // keeps the register peak down).
     float wf[W];
 #pragma unroll
     for (int i = 0; i < W; ++i) wf[i] = acc.weight(win.a[i], tmin);
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-        float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (wf[i] != 0.f) c = record_colour(vproj, win.id[i]);
-        acc.add(wf[i], c.y, c.z, c.w);
+    for (int i0 = 0; i0 < W; i0 += 4) {
+        float4 c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i0 + k < W && wf[i0 + k] != 0.f) c[k] = record_colour(vproj, win.id[i0 + k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k < W) acc.add(wf[i0 + k], c[k].y, c[k].z, c[k].w);
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     if (STATS) {
@@ -387,8 +395,14 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
 // starts new work at once instead of idling until its block's slowest wave
 // ends.  The counter must be zero at launch; every wave exits after drawing
 // a unit past the end.
+//
+// LDS per block: the four waves' staging slices (24 KB) and inboxes (15 KB),
+// so that four blocks fit a CU; with W <= 16 the kernel is held to 128 VGPRs,
+// which makes that four waves per SIMD.  The blend is bound by instruction
+// issue, and the fourth wave hides the latency of LDS reads and of the
+// record loads better than a larger inbox would save drains.
 template <int W, bool STATS, bool PERSIST>
-__global__ void __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(W <= 16 ? 3 : 1)))
+__global__ void __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(W <= 16 ? 4 : 1)))
 k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __restrict__ gids,
          const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ items, uint32_t n_items,
          uint32_t* __restrict__ counter, int batch, RenderViews views, Knobs kn,
@@ -396,7 +410,8 @@ k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __res
     __shared__ float4 stage[kRenderThreads / 64][kBatch][kStage];
     __shared__ float2 inbox[kRenderThreads / 64][kInbox][64];
     __shared__ uint32_t inbox_id[kRenderThreads / 64][kInbox][64];
-    const int slot = int(threadIdx.x) >> 6;
+    // Wave index, known to the compiler as wave-uniform (scalar registers).
+    const int slot = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
     if (!PERSIST) {
         render_unit<W, STATS>(items[blockIdx.x], slot, stage[slot], inbox[slot], inbox_id[slot], proj, n_gauss, gids,
                               ranges, views, kn, batch, stats);
@@ -407,7 +422,7 @@ k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __res
     for (;;) {
         uint32_t u = 0;
         if (lane == 0) u = atomicAdd(counter, 1u);
-        u = __shfl(u, 0);
+        u = __builtin_amdgcn_readfirstlane(u);
         if (u >= n_units) break;
         render_unit<W, STATS>(items[u >> 2], int(u & 3u), stage[slot], inbox[slot], inbox_id[slot], proj, n_gauss,
                               gids, ranges, views, kn, batch, stats);
