@@ -113,6 +113,13 @@ struct Accum {
         cg = fmaf(w, g, cg);
         cb = fmaf(w, b, cb);
     }
+    // add() for a colour that need not have been loaded when w = 0.
+    __device__ inline void add_if(float w, float r, float g, float b) {
+        const bool z = w == 0.f;
+        cr = z ? cr : fmaf(w, r, cr);
+        cg = z ? cg : fmaf(w, g, cg);
+        cb = z ? cb : fmaf(w, b, cb);
+    }
 };
 
 // Colour of Gaussian `gid` in a view's render records (fields 25..27, the
@@ -216,6 +223,29 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     // list ends, then push every lane's inbox through its window in arrival
     // order; repeat.  A single drain site keeps the window's registers apart
     // from the collecting loop's.
+    // One push of every lane's inbox entry i (a placeholder where the lane
+    // has fewer) through its window, blending the entry that leaves.
+    auto drain_step = [&](int i) {
+        const bool has = i < cnt;
+        if (STATS) ++n_push;
+        Slot x;
+        x.t = -INFINITY; x.a = 0.f; x.id = 0u;
+        if (has) {
+            const float2 v2 = ib[i][lane];
+            x.t = v2.x; x.a = v2.y; x.id = ibg[i][lane];
+        }
+        const Slot e = win.push(x);
+        const float w = acc.weight(e.a, tmin);
+        // Add the previous emission, whose colour load was issued one step
+        // earlier (a zero weight adds nothing), then issue this one's.  The
+        // load is unconditional so that it lands straight in the registers
+        // the next step reads: e.id is a list entry's Gaussian or the
+        // placeholder 0, and the wave has list entries, so the record exists.
+        acc.add_if(pw, pc.y, pc.z, pc.w);
+        pw = w;
+        pc = record_colour(vproj, e.id);
+    };
+
     uint32_t b0 = rg.x;          // first list entry of the staged batch
     uint64_t todo = 0;           // staged entries of the batch still to test
     bool staged = false;         // a batch is staged in this wave's slice
@@ -289,31 +319,23 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
                 break;
             }
         }
+        if (!full) break;
         // Drain: every lane pushes its inbox through its window in order.
-#pragma unroll 1
-        for (int i = 0; i < kCap; ++i) {
-            const bool has = i < cnt;
-            if (__ballot(has) == 0ull) break;  // wave-uniform
-            if (STATS) ++n_push;
-            Slot x;
-            x.t = -INFINITY; x.a = 0.f; x.id = 0u;
-            if (has) {
-                const float2 v2 = ib[i][lane];
-                x.t = v2.x; x.a = v2.y; x.id = ibg[i][lane];
-            }
-            const Slot e = win.push(x);
-            const float w = acc.weight(e.a, tmin);
-            // Add the previous emission, whose colour load was issued one
-            // step earlier, then issue this one's.
-            acc.add(pw, pc.y, pc.z, pc.w);
-            pw = w;
-            pc = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (w != 0.f) pc = record_colour(vproj, e.id);
-        }
+        // Some lane's inbox is full, so every step is needed; the steps are
+        // unrolled and unconditional, so the window stays in the same
+        // registers from step to step.
+#pragma unroll
+        for (int i = 0; i < kCap; ++i) drain_step(i);
         cnt = 0;
-        if (!full || __ballot(acc.alive) == 0ull) break;
+        if (__ballot(acc.alive) == 0ull) break;
     }
-    acc.add(pw, pc.y, pc.z, pc.w);
+    // The list ended (or every sample stopped): drain what is left.
+#pragma unroll 1
+    for (int i = 0; i < kCap; ++i) {
+        if (__ballot(i < cnt) == 0ull) break;  // wave-uniform
+        drain_step(i);
+    }
+    acc.add_if(pw, pc.y, pc.z, pc.w);
     // Flush the window in ascending depth order: weights first (they chain
     // through T), then the colours, four loads in flight at a time (which
     // keeps the register peak down).
