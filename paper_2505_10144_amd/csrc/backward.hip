@@ -134,7 +134,7 @@ __device__ inline float fixed_value(unsigned long long acc, int scale) {
     return float(ldexp(double(static_cast<long long>(acc)), scale - 54));
 }
 
-// Staged form of one list entry (7 float4, as in k_render): tile-relative
+// Staged form of one list entry (7 float4): tile-relative
 // mean offset, M, a3, log2 opacity, KAP, depth coefficients, colour.
 __device__ inline void stage_entry(const float4* rec, int ox, int oy, float4 out[7]) {
     const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
@@ -344,7 +344,8 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             const bool pass = alive && (h > 0.f) && (q <= f2.y * h2);
             if (__ballot(pass) != 0ull) {  // wave-uniform
                 const float4 f3 = st[3], f4 = st[4], f5 = st[5];
-                const float xa = pass ? fminf(amax, exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2))) : 0.f;
+                const float xa =
+                    pass ? fminf(amax, __builtin_amdgcn_exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2))) : 0.f;
                 const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
                 const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
                 const float w1 = fmaf(f4.y, dx, fmaf(f5.x, dy, f3.z));

@@ -303,7 +303,10 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
             }
             if (pass) {
                 const float4 f3 = st[j][3], f4 = st[j][4], f5 = st[j][5];
-                const float a = fminf(amax, exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2)));
+                // The hardware exp2 (no denormal range handling): a passing
+                // pair's exponent is at least log2(alpha_min), far inside the
+                // normal range, where it equals exp2f.
+                const float a = fminf(amax, __builtin_amdgcn_exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2)));
                 const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
                 const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
                 const float w1 = fmaf(f4.y, dx, fmaf(f5.x, dy, f3.z));
