@@ -8,19 +8,21 @@
 // in the same FP32 arithmetic, so it emits the same entries in the same
 // order.  Nothing per sample is stored by the forward pass; the replay needs
 // only the forward's final colour and transmittance (read back from the
-// output image).  At the i-th blended entry it knows T_i and the colour
-// accumulated so far, and forms
+// output image).  For the i-th blended entry of a sample it forms
 //   dL/dc_i     = g_rgb alpha_i T_i
 //   dL/dalpha_i = g_rgb . (c_i T_i - S_i / (1 - alpha_i)) + g_a T_fin / (1 - alpha_i),
 //   S_i         = (C_fin - C_<=i) + background T_fin   (the colour behind i),
-// then chains dL/dalpha through alpha = opacity 2^(-|z|^2 / h^2) to the 12
+// where only the scalar g_rgb . C_<=i of the running colour is needed, then
+// chains dL/dalpha through alpha = opacity 2^(-|z|^2 / h^2) to the 12
 // per-view splat parameters of the render record (M, a3, mean image point,
-// opacity, RGB).  The window holds (depth, alpha, arrival index).  The
-// records of the last three staged batches stay in a block-shared LDS ring
-// beside their gradient accumulators; a batch's sums go to the per-view
-// [Gaussian][12] buffer with one global atomic per value when the batch
-// leaves the ring.  A window entry emitted after its batch left the ring is
-// re-read from HBM and accumulated with global atomics.
+// opacity, RGB).  The window holds (depth, alpha, arrival index).  Emitted
+// pairs are queued per wave and their gradients computed a wave-full at a
+// time (see the kernel).  The records of the last three staged batches stay
+// in a block-shared LDS ring beside their gradient accumulators; a batch's
+// sums go to the per-view [Gaussian][12] buffer with one global atomic per
+// value when the batch leaves the ring.  A window entry emitted after its
+// batch left the ring is re-read from HBM and accumulated with global
+// atomics.
 //
 // The LDS accumulators are 64-bit fixed point, added with integer atomics:
 // on gfx950, LDS float atomics run far below the rate of LDS integer
@@ -134,30 +136,45 @@ __device__ inline float fixed_value(unsigned long long acc, int scale) {
     return float(ldexp(double(static_cast<long long>(acc)), scale - 54));
 }
 
-// Staged form of one list entry (7 float4): tile-relative
-// mean offset, M, a3, log2 opacity, KAP, depth coefficients, colour.
-__device__ inline void stage_entry(const float4* rec, int ox, int oy, float4 out[7]) {
+// Staged form of one list entry (6 float4): tile-relative mean offset, M,
+// a3, log2 opacity, KAP, the depth coefficients and the Gaussian's index.
+// The colour stays in the render record.
+__device__ inline void stage_entry(const float4* rec, uint32_t gid, int ox, int oy, float4 out[6]) {
     const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
-    const float4 p4 = rec[4], p5 = rec[5], p6 = rec[6];
+    const float4 p4 = rec[4], p5 = rec[5];
+    const float wy2 = reinterpret_cast<const float*>(rec)[24];
     out[0] = make_float4(float(ox - int(p0.x)) - p0.z, float(oy - int(p0.y)) - p0.w, p1.x, p1.y);
     out[1] = make_float4(p1.z, p1.w, p2.x, p2.y);
     out[2] = make_float4(p2.z, p2.w, p3.x, p3.y);
     out[3] = make_float4(p3.z, p4.x, p4.y, p4.z);
     out[4] = make_float4(p4.w, p5.x, p5.y, p5.z);
-    out[5] = make_float4(p5.w, p6.x, p6.y, p6.z);
-    out[6] = make_float4(p6.w, 0.f, 0.f, 0.f);
+    out[5] = make_float4(p5.w, wy2, __uint_as_float(gid), 0.f);
 }
+
+// Colour of Gaussian `gid` (render record fields 25..27: y, z, w of the
+// seventh float4).
+__device__ inline float4 bwd_colour(const float* __restrict__ vproj, uint32_t gid) {
+    return reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec)[6];
+}
+
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kQueue = 112;            // queued emissions per wave
+constexpr int kQueueGo = kQueue - 63;  // a round runs once this many are queued
 
 template <int W>
 __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restrict__ proj, uint32_t n_gauss,
                                                             const uint32_t* __restrict__ gids,
                                                             const uint32_t* __restrict__ ranges, BwdViews views,
                                                             Knobs kn, float* __restrict__ grad2d) {
-    __shared__ float4 ring[kRing][7];
-    __shared__ float4 ring_box[kRing];
+    __shared__ float4 ring[kRing][6];
     __shared__ unsigned long long acc[kRing][kG];
     __shared__ int acc_scale[kRing][kG];
-    __shared__ uint32_t ring_gid[kRing];
+    __shared__ float4 queue[kBwdThreads / 64][kQueue];
 
     const uint32_t item = blockIdx.x;
     int v = 0;
@@ -169,32 +186,41 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     const int sub = (T == 32) ? int(local & 3u) : 0;
     const int tx = int(tile % uint32_t(V.ntx)), ty = int(tile / uint32_t(V.ntx));
     const int ox = tx * T, oy = ty * T;
-    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
-    // Sample of this thread: the forward's quad-major 16x16 layout.
-    const int qd = t >> 2, kq = t & 3;
-    const int lx = 2 * (qd & 7) + (kq & 1), ly = 2 * (qd >> 3) + (kq >> 1);
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // Sample of a lane of this wave: the forward's quad-major 16x16 layout.
     const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
-    const int px = ox + bx + lx, py = oy + by + ly;
-    const float sx = float(bx + lx) + 0.5f, sy = float(by + ly) + 0.5f;
+    auto sample_of = [&](int l, float& sx_, float& sy_, int& px_, int& py_) {
+        const int tt = wv * 64 + l, qd = tt >> 2, kq = tt & 3;
+        const int lx = 2 * (qd & 7) + (kq & 1), ly = 2 * (qd >> 3) + (kq >> 1);
+        px_ = ox + bx + lx;
+        py_ = oy + by + ly;
+        sx_ = float(bx + lx) + 0.5f;
+        sy_ = float(by + ly) + 0.5f;
+    };
+    float sx, sy;
+    int px, py;
+    sample_of(lane, sx, sy, px, py);
     const bool inimg = px < V.W && py < V.H;
 
     // Forward final state and the incoming gradient of this sample.
     const size_t plane = size_t(V.W) * size_t(V.H);
-    float gr[3] = {0.f, 0.f, 0.f}, ga = 0.f, Cf[3] = {0.f, 0.f, 0.f}, Tf = 1.f;
+    float gr[3] = {0.f, 0.f, 0.f}, ga = 0.f, gCf = 0.f, Tf = 1.f;
     if (inimg) {
         const size_t pix = size_t(py) * V.W + px;
         Tf = 1.f - V.rgba[3 * plane + pix];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            gr[c] = V.grad[c * plane + pix];
-            Cf[c] = V.rgba[c * plane + pix] - Tf * kn.bg[c];
-        }
+        for (int c = 0; c < 3; ++c) gr[c] = V.grad[c * plane + pix];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gCf = fmaf(gr[c], V.rgba[c * plane + pix] - Tf * kn.bg[c], gCf);
         ga = V.grad[3 * plane + pix];
     }
     // The part of dL/dalpha_i (times 1 - alpha_i) that does not depend on i.
     const float gback = (ga - (gr[0] * kn.bg[0] + gr[1] * kn.bg[1] + gr[2] * kn.bg[2])) * Tf;
 
-    float Tc = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    float Tc = 1.f;
+    float D = 0.f;  // g_rgb . (colour accumulated so far)
     bool alive = inimg;
     BWindow<W> win;
     win.init();
@@ -208,47 +234,90 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     const float ry0 = float(oy + by + 4 * wv) + 0.5f, ry1 = float(oy + by + 4 * wv) + 3.5f;
     uint32_t ring_lo = 0;  // smallest arrival index whose record is still in the ring
 
-    // Blend the entry leaving the window (alpha ea, arrival index ek) and
-    // accumulate its gradient.  Called at wave-uniform points.
-    auto emit = [&](float ea, uint32_t ek) {
-        bool valid = alive && ek != kNone;
-        const float Tn = Tc * (1.f - ea);
-        if (valid && Tn < tmin) {  // stops the sample; not blended
-            alive = false;
-            valid = false;
+    // An emission (a blended (sample, entry) pair) is completed in three
+    // steps.  At the push that emits it, the lane advances T and issues the
+    // load of the entry's colour; the pair becomes the lane's pending one.
+    // At the lane's next emission (or a drain) the colour has arrived: the
+    // lane forms dL/dalpha from T, alpha and D = g_rgb . C (the colour in
+    // front), adds the pair's colour to D, and queues the record (dL/dalpha,
+    // weight T alpha, arrival index, lane).  Whenever enough records are
+    // queued, every lane of the wave takes one -- whichever sample it came
+    // from -- and accumulates its 12 gradient values, so the gradient work
+    // and the atomics run on full waves instead of on the few lanes that emit
+    // at a given push.
+    bool pend = false;
+    float p_T = 0.f, p_ea = 0.f;
+    uint32_t p_ek = 0;
+    float4 pc = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t qhead = 0, qcount = 0;  // wave-uniform: ring-buffer head and length
+
+    // Fold every pending pair into a queue record.
+    auto fold = [&]() {
+        bool rec = pend;
+        float rdA = 0.f, rw = 0.f;
+        if (pend) {
+            const float gc = fmaf(gr[0], pc.y, fmaf(gr[1], pc.z, gr[2] * pc.w));
+            const float w = p_T * p_ea;
+            const float inv1 = 1.f / (1.f - p_ea);
+            // dL/dalpha = g_rgb . (c T - S / (1 - alpha)) + g_a T_fin / (1 - alpha),
+            // S = C_fin - C_<=i (+ background T_fin, folded into gback).
+            rdA = fmaf(gback - (gCf - fmaf(w, gc, D)), inv1, p_T * gc);
+            D = fmaf(w, gc, D);
+            rw = w;
         }
-        const uint64_t vm = __ballot(valid);
-        if (vm == 0ull) return;
-        float g[kG];
-#pragma unroll
-        for (int k = 0; k < kG; ++k) g[k] = 0.f;
-        const bool in_ring = ek >= ring_lo;
-        const int sl = int(ek % uint32_t(kRing));
-        uint32_t gid = 0;
-        if (valid) {
-            float4 e[7];
+        pend = false;
+        const uint64_t rm = __ballot(rec);
+        if (rm == 0ull) return;
+        if (rec) {
+            uint32_t pos = qhead + qcount + uint32_t(__popcll(rm & lt));
+            pos = pos >= uint32_t(kQueue) ? pos - uint32_t(kQueue) : pos;
+            pos = pos >= uint32_t(kQueue) ? pos - uint32_t(kQueue) : pos;
+            queue[wv][pos] = make_float4(rdA, rw, __uint_as_float(p_ek), __int_as_float(lane));
+        }
+        qcount += uint32_t(__popcll(rm));
+    };
+
+    // One round: lane l takes the l-th queued record.
+    auto round = [&]() {
+        wave_sync_lds();
+        const uint32_t nq = qcount < 64u ? qcount : 64u;
+        const bool has = uint32_t(lane) < nq;
+        float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (has) {
+            uint32_t pos = qhead + uint32_t(lane);
+            pos = pos >= uint32_t(kQueue) ? pos - uint32_t(kQueue) : pos;
+            r = queue[wv][pos];
+        }
+        const int pl = has ? __float_as_int(r.w) : 0;
+        // g_rgb of the record's sample, from the lane that owns it.
+        const float pg0 = __shfl(gr[0], pl), pg1 = __shfl(gr[1], pl), pg2 = __shfl(gr[2], pl);
+        if (has) {
+            const float dA = r.x, w = r.y;
+            const uint32_t ek = __float_as_uint(r.z);
+            float qsx, qsy;
+            int qpx, qpy;
+            sample_of(pl, qsx, qsy, qpx, qpy);
+            const bool in_ring = ek >= ring_lo;
+            const int sl = int(ek % uint32_t(kRing));
+            float4 e[6];
             if (in_ring) {
 #pragma unroll
-                for (int k = 0; k < 7; ++k) e[k] = ring[sl][k];
-                gid = ring_gid[sl];
+                for (int k = 0; k < 6; ++k) e[k] = ring[sl][k];
             } else {
-                gid = gids[rg.x + ek];
-                stage_entry(reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec), ox, oy, e);
+                const uint32_t gid = gids[rg.x + ek];
+                stage_entry(reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec), gid, ox, oy, e);
             }
-            const float cr = e[5].z, cg = e[5].w, cb = e[6].x;
-            const float w = Tc * ea;
-            const float n0 = fmaf(w, cr, C0), n1 = fmaf(w, cg, C1), n2 = fmaf(w, cb, C2);
-            const float inv1 = 1.f / (1.f - ea);
-            float dA = gr[0] * (cr * Tc - (Cf[0] - n0) * inv1);
-            dA = fmaf(gr[1], cg * Tc - (Cf[1] - n1) * inv1, dA);
-            dA = fmaf(gr[2], cb * Tc - (Cf[2] - n2) * inv1, dA);
-            dA = fmaf(gback, inv1, dA);
-            g[G_RGB] = gr[0] * w;
-            g[G_RGB + 1] = gr[1] * w;
-            g[G_RGB + 2] = gr[2] * w;
+            const uint32_t gid = __float_as_uint(e[5].z);
+            float g[kG];
+#pragma unroll
+            for (int k = 0; k < kG; ++k) g[k] = 0.f;
+            // dL/dcolour = g_rgb of the pair's sample times its weight.
+            g[G_RGB] = pg0 * w;
+            g[G_RGB + 1] = pg1 * w;
+            g[G_RGB + 2] = pg2 * w;
             // alpha = opacity 2^(-E), E = q / h^2, q = |M delta|^2, delta =
             // sample - mean; a clamped alpha passes no gradient to the splat.
-            const float dx = e[0].x + sx, dy = e[0].y + sy;
+            const float dx = e[0].x + qsx, dy = e[0].y + qsy;
             const float M00 = e[0].z, M01 = e[0].w, M10 = e[1].x, M11 = e[1].y;
             const float a3x = e[1].z, a3y = e[1].w;
             const float z1 = fmaf(M00, dx, M01 * dy);
@@ -273,12 +342,6 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
                 g[G_XY + 1] = -(cz * fmaf(z1, M01, z2 * M11) + ch * a3y);
                 g[G_SIG] = dA * exp2f(-E);
             }
-            C0 = n0;
-            C1 = n1;
-            C2 = n2;
-            Tc = Tn;
-        }
-        if (valid) {
             float* dst = vgrad + size_t(gid) * kG;
 #pragma unroll
             for (int k = 0; k < kG; ++k) {
@@ -286,6 +349,40 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
                 if (!in_ring || !fixed_add(&acc[sl][k], &acc_scale[sl][k], g[k])) unsafeAtomicAdd(dst + k, g[k]);
             }
         }
+        qhead += nq;
+        qhead = qhead >= uint32_t(kQueue) ? qhead - uint32_t(kQueue) : qhead;
+        qcount -= nq;
+    };
+
+    // Blend the entry leaving the window (alpha ea, arrival index ek).
+    // Called at wave-uniform points.
+    auto emit = [&](float ea, uint32_t ek) {
+        bool valid = alive && ek != kNone;
+        const float Tn = Tc * (1.f - ea);
+        if (valid && Tn < tmin) {  // stops the sample; not blended
+            alive = false;
+            valid = false;
+        }
+        if (__ballot(valid) == 0ull) return;
+        fold();
+        if (valid) {
+            const bool in_ring = ek >= ring_lo;
+            const uint32_t gid =
+                in_ring ? __float_as_uint(ring[ek % uint32_t(kRing)][5].z) : gids[rg.x + ek];
+            pc = bwd_colour(vproj, gid);
+            pend = true;
+            p_T = Tc;
+            p_ea = ea;
+            p_ek = ek;
+            Tc = Tn;
+        }
+        if (qcount >= uint32_t(kQueueGo)) round();
+    };
+
+    // Complete every pending pair and empty the queue.
+    auto drain = [&]() {
+        fold();
+        while (qcount > 0u) round();
     };
 
     uint32_t last_b0 = 0, staged_end = 0;
@@ -301,20 +398,18 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
                 const int s = base + w / kG, k = w % kG;
                 const int sc = acc_scale[s][k];
                 if (sc != kUnset && acc[s][k] != 0ull)
-                    unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], fixed_value(acc[s][k], sc));
+                    unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[s][5].z)) * kG + k],
+                                    fixed_value(acc[s][k], sc));
             }
             __syncthreads();
             ring_lo = b0 + kBwdBatch - kRing;
         }
         if (t < nb) {
             const uint32_t gid = gids[rg.x + b0 + t];
-            const float4* rec = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec);
-            float4 e[7];
-            stage_entry(rec, ox, oy, e);
+            float4 e[6];
+            stage_entry(reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec), gid, ox, oy, e);
 #pragma unroll
-            for (int k = 0; k < 7; ++k) ring[base + t][k] = e[k];
-            ring_box[base + t] = rec[7];
-            ring_gid[base + t] = gid;
+            for (int k = 0; k < 6; ++k) ring[base + t][k] = e[k];
         }
         for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
             acc[base + w / kG][w % kG] = 0ull;
@@ -322,12 +417,14 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         }
         last_b0 = b0;
         staged_end = b0 + uint32_t(nb);
-        __syncthreads();
+        // Each wave reads the boxes of the batch for its own culling.
         bool rel = false;
         if (lane < nb) {
-            const float4 bb = ring_box[base + lane];
+            const uint32_t gid = gids[rg.x + b0 + lane];
+            const float4 bb = reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec)[7];
             rel = !(bb.z < rx0 || bb.x > rx1 || bb.w < ry0 || bb.y > ry1);
         }
+        __syncthreads();
         uint64_t todo = __ballot(rel);
         if (__ballot(alive) == 0ull) todo = 0ull;
         while (todo) {
@@ -359,6 +456,9 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             }
             if (__ballot(alive) == 0ull) break;
         }
+        // Every emission is accumulated before the next batch may leave
+        // the ring.
+        drain();
     }
     // Flush the window in ascending depth order.
 #pragma unroll 1
@@ -368,6 +468,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         win.shift();
         emit(ea, ek);
     }
+    drain();
     __syncthreads();
     // Flush what is left in the ring: arrival indices [first, staged_end).
     const uint32_t span = uint32_t(kRing - kBwdBatch);
@@ -378,7 +479,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         if (a >= staged_end) continue;
         const int sc = acc_scale[s][k];
         if (sc != kUnset && acc[s][k] != 0ull)
-            unsafeAtomicAdd(&vgrad[size_t(ring_gid[s]) * kG + k], fixed_value(acc[s][k], sc));
+            unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[s][5].z)) * kG + k], fixed_value(acc[s][k], sc));
     }
 }
 

@@ -310,6 +310,64 @@ def test_sort_pairs_bit_exact_on_gpu_keys(R):
     assert np.array_equal(rg, otiles.tile_ranges(ks[:n_kept], r.tiles_total))
 
 
+def _copies_scene(n_copies, n_random):
+    """n_copies identical Gaussians (equal keys in every tile they reach) and
+    n_random random ones."""
+    a = synth.uniform_scene(11, 1, lo=-0.2, hi=0.2, log_scale=(-1.5, 0.0))
+    a.opacity_logits[:] = 3.0
+    b = synth.uniform_scene(12, n_random, lo=-1.0, hi=1.0)
+    rep = lambda x, y: np.concatenate([np.repeat(x, n_copies, axis=-1), y], axis=-1)
+    return synth.Scene(rep(a.means, b.means), rep(a.log_scales, b.log_scales), rep(a.quats, b.quats),
+                       rep(a.opacity_logits, b.opacity_logits), rep(a.sh, b.sh), a.sh_degree)
+
+
+@pytest.mark.parametrize("case", ["small", "copies", "stereo_full"])
+def test_render_sort_is_stable_sort_of_candidates(R, case):
+    """vrs_sort leaves the kept candidates exactly in stable (tile, depth)
+    order -- ties in candidate order -- with matching ranges, also for tile
+    lists longer than 2048 entries and runs of equal keys that long."""
+    print(f"[render sort] {case}", flush=True)
+    if case == "small":
+        scene, cams, fovs, params = synth.config_stereo(3, n=8000, width=256, height=224)
+    elif case == "copies":
+        scene = _copies_scene(3000, 2000)
+        cams = [synth.camera_translate((0.0, 0.0, -2.0), 90.0, 200, 160)]
+        fovs = [synth.fovea_off()]
+        params = synth.default_params(tile=16, window=8)
+    else:
+        scene, cams, fovs, params = synth.config_stereo(0)
+    r = R.Renderer(cams, fovs, params, scene.n)
+    g = R.upload(scene)
+    r.ensure_capacity(g)
+    r.preprocess(g)
+    r.duplicate(g)
+    torch.cuda.synchronize()
+    r.check()
+    n = int(r.n_inst[0].item())
+    k0 = r.keys[:n].cpu().numpy().view(np.uint64).copy()
+    v0 = r.gids[:n].cpu().numpy().view(np.uint32).copy()
+    r.sort(g)
+    torch.cuda.synchronize()
+    r.check()
+    n_kept = int(r.n_inst[1].item())
+    live = k0 != np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert int(live.sum()) == n_kept
+    order = np.argsort(k0[live], kind="stable")
+    ks = r.keys[:n_kept].cpu().numpy().view(np.uint64)
+    vs = r.gids[:n_kept].cpu().numpy().view(np.uint32)
+    assert np.array_equal(ks, k0[live][order]) and np.array_equal(vs, v0[live][order])
+    rg = r.ranges[: 2 * r.tiles_total].cpu().numpy().view(np.uint32).reshape(-1, 2)
+    assert np.array_equal(rg, otiles.tile_ranges(ks, r.tiles_total))
+    lens = rg[:, 1].astype(np.int64) - rg[:, 0]
+    print(f"[render sort] {n_kept} kept of {n}, longest list {int(lens.max())}", flush=True)
+    if case != "small":
+        assert lens.max() > 2048
+    if case == "copies":
+        # Some tile holds a run of equal keys longer than 2048.
+        _, runs = np.unique(ks, return_counts=True)
+        assert runs.max() > 2048
+
+
 @pytest.mark.parametrize("n,bits,dups", [(0, 40, 1), (1, 40, 1), (4095, 64, 1), (4097, 33, 7),
                                          (100_003, 46, 50), (300_000, 64, 1000), (3_000_001, 64, 3),
                                          (2_500_000, 8, 1)])
