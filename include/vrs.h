@@ -132,8 +132,9 @@ typedef struct {
 /* Buffer sizes for one configuration (all bytes unless noted). */
 typedef struct {
     size_t proj_bytes;       /* per view and Gaussian: a 128-byte FP32 render record
-                                ([n_views][n][32] floats) followed, after all of them,
-                                by a 224-byte FP64 tile-test record                  */
+                                ([n_views][n][32] floats); after all of them a
+                                224-byte FP64 tile-test record each; after those a
+                                float4 colour (r, g, b, 0) each                      */
     size_t counts_bytes;     /* uint32 counts[n_views][n]                         */
     uint32_t tiles_total;    /* sum over views of sort-grid tiles (ranges rows)    */
     uint32_t items_max;      /* upper bound on render work items                   */
@@ -166,8 +167,8 @@ int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_vi
 /* Per-Gaussian preprocessing (Sec. 3 Eq. 1, Optimal Projection of Sec. 3 end
  * and Sec. 4.2, SH colour; one thread per Gaussian covering every view).
  * Writes into `proj` (proj_bytes, 16-byte aligned) each Gaussian's FP32
- * render record per view -- rows [n_views][n][VRS_RECORD_FLOATS] -- and its
- * FP64 tile-test record, and into counts[n_views][n] the number of candidate
+ * render record per view -- rows [n_views][n][VRS_RECORD_FLOATS] -- its
+ * FP64 tile-test record and its colour, and into counts[n_views][n] the number of candidate
  * tiles: the tiles meeting the image of the cone of directions in which the
  * splat can reach alpha_min (a conservative bound; the exact tile test of
  * Eq. 4 runs in vrs_duplicate).  Culled Gaussians (camera z <= z_near,

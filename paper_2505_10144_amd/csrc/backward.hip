@@ -138,7 +138,7 @@ __device__ inline float fixed_value(unsigned long long acc, int scale) {
 
 // Staged form of one list entry (6 float4): tile-relative mean offset, M,
 // a3, log2 opacity, KAP, the depth coefficients and the Gaussian's index.
-// The colour stays in the render record.
+// The colour stays in the colour array.
 __device__ inline void stage_entry(const float4* rec, uint32_t gid, int ox, int oy, float4 out[6]) {
     const float4 p0 = rec[0], p1 = rec[1], p2 = rec[2], p3 = rec[3];
     const float4 p4 = rec[4], p5 = rec[5];
@@ -151,11 +151,8 @@ __device__ inline void stage_entry(const float4* rec, uint32_t gid, int ox, int 
     out[5] = make_float4(p5.w, wy2, __uint_as_float(gid), 0.f);
 }
 
-// Colour of Gaussian `gid` (render record fields 25..27: y, z, w of the
-// seventh float4).
-__device__ inline float4 bwd_colour(const float* __restrict__ vproj, uint32_t gid) {
-    return reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec)[6];
-}
+// Colour (x, y, z) of Gaussian `gid` in a view's slice of the colour array.
+__device__ inline float4 bwd_colour(const float4* __restrict__ vcol, uint32_t gid) { return vcol[gid]; }
 
 __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -229,6 +226,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
     const uint32_t L = rg.y - rg.x;
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
+    const float4* vcol = colour_array(proj, size_t(views.n) * size_t(n_gauss)) + size_t(v) * size_t(n_gauss);
     float* vgrad = grad2d + size_t(v) * size_t(n_gauss) * kG;
     const float rx0 = float(ox + bx) + 0.5f, rx1 = float(ox + bx) + 15.5f;
     const float ry0 = float(oy + by + 4 * wv) + 0.5f, ry1 = float(oy + by + 4 * wv) + 3.5f;
@@ -256,7 +254,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         bool rec = pend;
         float rdA = 0.f, rw = 0.f;
         if (pend) {
-            const float gc = fmaf(gr[0], pc.y, fmaf(gr[1], pc.z, gr[2] * pc.w));
+            const float gc = fmaf(gr[0], pc.x, fmaf(gr[1], pc.y, gr[2] * pc.z));
             const float w = p_T * p_ea;
             const float inv1 = 1.f / (1.f - p_ea);
             // dL/dalpha = g_rgb . (c T - S / (1 - alpha)) + g_a T_fin / (1 - alpha),
@@ -369,7 +367,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             const bool in_ring = ek >= ring_lo;
             const uint32_t gid =
                 in_ring ? __float_as_uint(ring[ek % uint32_t(kRing)][5].z) : gids[rg.x + ek];
-            pc = bwd_colour(vproj, gid);
+            pc = bwd_colour(vcol, gid);
             pend = true;
             p_T = Tc;
             p_ea = ea;

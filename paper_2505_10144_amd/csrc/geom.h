@@ -62,7 +62,7 @@ struct TileGeo {
     double w0[3], wx[3], wy[3];  // denominator |w0 + dx wx + dy wy|^2
     int32_t tx0, ty0, ncx, count;  // candidate tile box origin, width, count
 };
-static_assert(sizeof(TileGeo) == 224, "TileGeo layout");
+static_assert(sizeof(TileGeo) == kTileGeoBytes, "TileGeo layout");
 
 // Everything K1 derives for one Gaussian in one view.
 struct Geo {

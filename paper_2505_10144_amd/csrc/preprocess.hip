@@ -71,8 +71,8 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
         t.count = ncx * ncy;
         counts[slot] = uint32_t(ncx * ncy);
         tgeo[slot] = t;
-        // Render record (field map in vrs_internal.h); the colour (fields
-        // 25..27) is written by k_color.
+        // Render record (field map in vrs_internal.h); the colour goes to
+        // the colour array (k_color).
         const double xi = floor(t.x0), yi = floor(t.y0);
         const float zs = float(sqrt(0.5 / M_LN2));  // |z|^2 = (log2 e / 2) D^2
         float4* dst = reinterpret_cast<float4*>(proj + slot * kRec);
@@ -88,8 +88,9 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
 }
 
 // View-dependent colour of every Gaussian in every view from its SH
-// coefficients (kept apart from k_preprocess so that the 48 coefficients do
-// not occupy registers across the FP64 set-up).  Views go in groups of four:
+// coefficients, written to the colour array as one float4 per slot (kept
+// apart from k_preprocess so that the 48 coefficients do not occupy
+// registers across the FP64 set-up).  Views go in groups of four:
 // each coefficient is read once per group and applied to all of its views,
 // so a stereo pair reads the coefficients from HBM once.  Culled
 // Gaussian-views get a colour too; no list refers to them.
@@ -100,6 +101,7 @@ __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, floa
     if (i >= g.n) return;
     const int n = g.n;
     const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    float4* cols = const_cast<float4*>(colour_array(proj, size_t(views.n) * size_t(n)));
     const double mu[3] = {double(g.means[i]), double(g.means[n + i]), double(g.means[2 * n + i])};
     for (int v0 = 0; v0 < views.n; v0 += kColorViews) {
         float Y[kColorViews][16];
@@ -131,10 +133,8 @@ __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, floa
 #pragma unroll
         for (int j = 0; j < kColorViews; ++j) {
             if (v0 + j < views.n) {
-                float* dst = proj + (size_t(v0 + j) * size_t(n) + size_t(i)) * kRec + R_RGB;
-                dst[0] = fmaxf(rgb[j][0], 0.f);
-                dst[1] = fmaxf(rgb[j][1], 0.f);
-                dst[2] = fmaxf(rgb[j][2], 0.f);
+                cols[size_t(v0 + j) * size_t(n) + size_t(i)] =
+                    make_float4(fmaxf(rgb[j][0], 0.f), fmaxf(rgb[j][1], 0.f), fmaxf(rgb[j][2], 0.f), 0.f);
             }
         }
     }
@@ -239,7 +239,6 @@ __global__ void k_dup_init(uint32_t* n_inst, size_t capacity, int* status) {
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
-size_t tgeo_offset_bytes(size_t nslots) { return nslots * kRec * sizeof(float); }
 
 int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn, float* proj,
                       uint32_t* counts, hipStream_t s) {

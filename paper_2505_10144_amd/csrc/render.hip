@@ -122,11 +122,8 @@ struct Accum {
     }
 };
 
-// Colour of Gaussian `gid` in a view's render records (fields 25..27, the
-// y, z, w of the record's seventh float4).
-__device__ inline float4 record_colour(const float* __restrict__ vproj, uint32_t gid) {
-    return reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec)[6];
-}
+// Colour (x, y, z) of Gaussian `gid` in a view's slice of the colour array.
+__device__ inline float4 gauss_colour(const float4* __restrict__ vcol, uint32_t gid) { return vcol[gid]; }
 
 __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -199,6 +196,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
 
     const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
+    const float4* vcol = colour_array(proj, size_t(views.n) * size_t(n_gauss)) + size_t(v) * size_t(n_gauss);
     const float amax = kn.alpha_max, tmin = kn.t_min;
     uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0, n_push = 0;
     int cnt = 0;  // entries in this lane's inbox
@@ -241,9 +239,9 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
         // load is unconditional so that it lands straight in the registers
         // the next step reads: e.id is a list entry's Gaussian or the
         // placeholder 0, and the wave has list entries, so the record exists.
-        acc.add_if(pw, pc.y, pc.z, pc.w);
+        acc.add_if(pw, pc.x, pc.y, pc.z);
         pw = w;
-        pc = record_colour(vproj, e.id);
+        pc = gauss_colour(vcol, e.id);
     };
 
     uint32_t b0 = rg.x;          // first list entry of the staged batch
@@ -338,7 +336,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
         if (__ballot(i < cnt) == 0ull) break;  // wave-uniform
         drain_step(i);
     }
-    acc.add_if(pw, pc.y, pc.z, pc.w);
+    acc.add_if(pw, pc.x, pc.y, pc.z);
     // Flush the window in ascending depth order: weights first (they chain
     // through T), then the colours, four loads in flight at a time (which
     // keeps the register peak down).
@@ -351,11 +349,11 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             c[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (i0 + k < W && wf[i0 + k] != 0.f) c[k] = record_colour(vproj, win.id[i0 + k]);
+            if (i0 + k < W && wf[i0 + k] != 0.f) c[k] = gauss_colour(vcol, win.id[i0 + k]);
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (i0 + k < W) acc.add(wf[i0 + k], c[k].y, c[k].z, c[k].w);
+            if (i0 + k < W) acc.add(wf[i0 + k], c[k].x, c[k].y, c[k].z);
         __builtin_amdgcn_sched_barrier(0);
     }
 

@@ -28,10 +28,22 @@ enum RecField : int {
     R_SIG = 15,              // opacity
     R_W0 = 16,               // depth denominator |w0 + dx wx + dy wy|^2 (w0: 16..18,
     R_WX = 19, R_WY = 22,    //   wx: 19..21, wy: 22..24)
-    R_RGB = 25,              // colour 25..27
+    R_FREE = 25,             // 25..27 unused (colours are in the colour array)
     R_BOX = 28,              // pixel box (x0, y0, x1, y1) holding every sample
                              //   where alpha can reach alpha_min
 };
+
+// Layout of the `proj` buffer for nslots = n_views * n (view-major) slots:
+// the FP32 render records, then the FP64 tile-test records (224 bytes
+// each), then one float4 colour (r, g, b, 0) per slot.
+constexpr size_t kTileGeoBytes = 224;
+__host__ __device__ inline size_t tgeo_offset_bytes(size_t nslots) { return nslots * kRec * sizeof(float); }
+__host__ __device__ inline size_t colour_offset_bytes(size_t nslots) {
+    return nslots * (kRec * sizeof(float) + kTileGeoBytes);
+}
+__host__ __device__ inline const float4* colour_array(const float* proj, size_t nslots) {
+    return reinterpret_cast<const float4*>(reinterpret_cast<const char*>(proj) + colour_offset_bytes(nslots));
+}
 
 struct GaussPtrs {
     const float* means;

@@ -265,3 +265,9 @@ class Renderer:
     def records(self) -> torch.Tensor:
         return self.proj[: self.V * self.n * L.VRS_RECORD_FLOATS * 4].view(torch.float32).view(
             self.V, self.n, L.VRS_RECORD_FLOATS)
+
+    def colours(self) -> torch.Tensor:
+        """[V][n][4] float32: each Gaussian's colour (r, g, b, 0) per view,
+        after the render and tile-test records in `proj`."""
+        off = self.V * self.n * (L.VRS_RECORD_FLOATS * 4 + L.TILEGEO_BYTES)
+        return self.proj[off: off + self.V * self.n * 16].view(torch.float32).view(self.V, self.n, 4)

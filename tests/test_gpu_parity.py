@@ -423,16 +423,18 @@ def test_capacity_overflow_is_reported_and_recoverable(R):
 
 
 def test_record_colours_and_alpha(R):
-    """K1 records: colour equals the oracle's SH colour, and alpha evaluated
-    from the record formula at the mean's pixel equals the oracle's."""
+    """K1 output: the colour array holds the oracle's SH colour, and the
+    record's mean image point and opacity equal the oracle's."""
     scene, cams, fovs, params = synth.config_stereo(6, n=3000, width=256, height=224)
     r, g = _stage_setup(R, scene, cams, fovs, params)
     rec = r.records().cpu().numpy().astype(np.float64)
+    cols = r.colours().cpu().numpy().astype(np.float64)
     from oracle.render import preprocess_view
     for v, cam in enumerate(cams):
         pre = preprocess_view(scene, cam, params)
         ok = pre["valid"]
-        np.testing.assert_allclose(rec[v, ok, 25:28], pre["color"][ok], atol=2e-6)
+        np.testing.assert_allclose(cols[v, ok, :3], pre["color"][ok], atol=2e-6)
+        assert np.all(cols[v, :, 3] == 0.0)
         x0 = rec[v, ok, 0] + rec[v, ok, 2]
         y0 = rec[v, ok, 1] + rec[v, ok, 3]
         np.testing.assert_allclose(x0, pre["x0"][ok], atol=1e-4, rtol=1e-6)
