@@ -454,13 +454,16 @@ k_render(const float* __restrict__ proj, uint32_t n_gauss, const uint32_t* __res
 
 // K7: LOW pixels of a foveated view take the 3x3 binomial blur of the
 // nearest-neighbour-upsampled image (coordinates clamped to the image); other
-// pixels are copied.  One block per 64x4 tile (a wave reads whole 256-byte
-// row segments of each plane).  Workgroups are dealt to the
+// pixels are copied.  One block per 64x16 tile: a thread owns a column of
+// four output pixels and reads the six rows their windows span once each (a
+// wave reads whole 256-byte row segments of each plane).  Workgroups are dealt to the
 // eight XCDs round-robin, and each XCD has its own L2; the block index is
 // remapped so that every XCD gets a contiguous band of tile rows, whose
 // blur halos then hit in that XCD's L2 instead of being fetched again by a
 // neighbour XCD.
 constexpr uint32_t kXcds = 8;
+
+constexpr int kComposeRows = 4;  // output rows per thread
 
 __global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __restrict__ cls, uint32_t ntiles,
                                                  uint32_t per_xcd) {
@@ -468,29 +471,36 @@ __global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __
     if (tid >= ntiles) return;
     const uint32_t ntx = uint32_t(V.W + 63) / 64;
     const int x = int(tid % ntx) * 64 + int(threadIdx.x & 63);
-    const int y = int(tid / ntx) * 4 + int(threadIdx.x >> 6);
-    if (x >= V.W || y >= V.H) return;
+    const int y0 = (int(tid / ntx) * 4 + int(threadIdx.x >> 6)) * kComposeRows;
+    if (x >= V.W || y0 >= V.H) return;
     const size_t plane = size_t(V.W) * size_t(V.H);
-    const uint8_t c = cls[V.cls_off + size_t(y >> 4) * V.ntx16 + (x >> 4)];
-    const size_t off = size_t(y) * V.W + x;
-    if (c != VRS_CLASS_LOW) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) V.out[k * plane + off] = V.pre[k * plane + off];
-        return;
-    }
     const int xs[3] = {max(x - 1, 0), x, min(x + 1, V.W - 1)};
-    const int ys[3] = {max(y - 1, 0), y, min(y + 1, V.H - 1)};
-    const float wk[3] = {1.f, 2.f, 1.f};
+    // Rows y0 - 1 .. y0 + kComposeRows (clamped): each is read once and
+    // serves the three outputs whose window holds it.
+    int ry[kComposeRows + 2];
+#pragma unroll
+    for (int r = 0; r < kComposeRows + 2; ++r) ry[r] = min(max(y0 - 1 + r, 0), V.H - 1);
+    uint8_t c[kComposeRows];
+#pragma unroll
+    for (int r = 0; r < kComposeRows; ++r)
+        c[r] = cls[V.cls_off + size_t(min(y0 + r, V.H - 1) >> 4) * V.ntx16 + (x >> 4)];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float* p = V.pre + k * plane;
-        float s = 0.f;
+        float h[kComposeRows + 2], mid[kComposeRows + 2];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float* row = p + size_t(ys[a]) * V.W;
-            s = fmaf(wk[a], fmaf(wk[0], row[xs[0]], fmaf(wk[1], row[xs[1]], wk[2] * row[xs[2]])), s);
+        for (int r = 0; r < kComposeRows + 2; ++r) {
+            const float* row = p + size_t(ry[r]) * V.W;
+            const float a = row[xs[0]], b = row[xs[1]], d = row[xs[2]];
+            h[r] = fmaf(1.f, a, fmaf(2.f, b, d));  // horizontal 1-2-1
+            mid[r] = b;
         }
-        V.out[k * plane + off] = s * (1.f / 16.f);
+#pragma unroll
+        for (int r = 0; r < kComposeRows; ++r) {
+            if (y0 + r >= V.H) break;
+            const float s = fmaf(1.f, h[r + 2], fmaf(2.f, h[r + 1], h[r]));
+            V.out[k * plane + size_t(y0 + r) * V.W + x] = c[r] == VRS_CLASS_LOW ? s * (1.f / 16.f) : mid[r + 1];
+        }
     }
 }
 
@@ -614,7 +624,7 @@ int launch_compose(const RenderViews& views, const uint8_t* cls, hipStream_t s) 
     for (int v = 0; v < views.n; ++v) {
         const RenderView& V = views.v[v];
         if (!V.foveated) continue;
-        const uint32_t ntiles = uint32_t((V.W + 63) / 64) * uint32_t((V.H + 3) / 4);
+        const uint32_t ntiles = uint32_t((V.W + 63) / 64) * uint32_t((V.H + 4 * kComposeRows - 1) / (4 * kComposeRows));
         const uint32_t per = (ntiles + kXcds - 1) / kXcds;
         hipLaunchKernelGGL(k_compose, dim3(per * kXcds), dim3(256), 0, s, V, cls, ntiles, per);
     }
