@@ -233,10 +233,10 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
  * is a device pointer to view v's output, planar float [4][height][width]
  * (R, G, B, alpha = 1 - T).  `plan` and n_items come from vrs_fovea_plan for
  * the same cameras/foveas/params; `ws` (256-byte aligned) must hold
- * render_ws_bytes.  The work items run longest first: before the blend, one
- * radix pass orders them by the length of their tile's list on a log scale
- * (equal keys keep plan order), which changes the scheduling only, never
- * the output. */
+ * render_ws_bytes.  The work items run longest first: before the blend, a
+ * one-block counting sort orders them by the length of their tile's list
+ * on a log scale (the order within a key is unspecified), which changes the
+ * scheduling only, never the output. */
 int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const uint32_t* ranges,
                         const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
                         const vrs_params* p, const void* plan, uint32_t n_items,

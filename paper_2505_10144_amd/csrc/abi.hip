@@ -12,11 +12,11 @@ int launch_status(hipError_t e) { return e == hipSuccess ? VRS_OK : VRS_ERR_HIP;
 // Launchers defined in the kernel translation units.
 int launch_preprocess(const GaussPtrs&, const GeoViews&, const Knobs&, float*, uint32_t*, hipStream_t);
 int launch_duplicate(const GaussPtrs&, const GeoViews&, const Knobs&, const float*, const uint32_t*, uint64_t*,
-                     uint32_t*, size_t, uint32_t*, void*, int*, hipStream_t);
+                     uint32_t*, size_t, uint32_t*, void*, int*, hipStream_t, bool);
 size_t sort_ws_bytes(size_t capacity);
 int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, int*, hipStream_t);
 int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*, bool, size_t, int, void*, int*,
-                         hipStream_t);
+                         hipStream_t, uint32_t*);
 
 // Bytes per Gaussian and view in `proj`: the FP32 render record plus the FP64
 // tile-test record (TileGeo, 224 bytes) that instantiation reads.
@@ -194,6 +194,26 @@ int key_bits_for(uint32_t tiles_total) {
 
 }  // namespace
 
+static int duplicate_impl(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
+                          int32_t n_views, const vrs_params* p, const void* proj, const uint32_t* counts,
+                          uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev, void* ws,
+                          size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream, bool count_live) {
+    int rc = check_gaussians(g);
+    if (rc != VRS_OK) return rc;
+    Layout L;
+    rc = make_layout(cams, foveas, n_views, p, L);
+    if (rc != VRS_OK) return rc;
+    const size_t nv = size_t(n_views) * size_t(g->n);
+    if (!n_inst_dev || (nv > 0 && (!counts || !ws || !proj)) || (capacity > 0 && (!keys || !gids)))
+        return VRS_ERR_INVALID_ARG;
+    if (capacity > 0xFFFFFFFFull || nv > 0xFFFFFFFFull) return VRS_ERR_UNSUPPORTED;
+    if (ws_bytes < dup_ws_bytes(nv) || !aligned(keys, 8) || !aligned(ws, 16) || !aligned(proj, 16))
+        return VRS_ERR_INVALID_ARG;
+    return launch_duplicate(gauss_ptrs(g), geo_views(cams, L, p), knobs(p), static_cast<const float*>(proj), counts,
+                            keys, gids, capacity, n_inst_dev, ws, status_dev, reinterpret_cast<hipStream_t>(stream),
+                            count_live);
+}
+
 extern "C" {
 
 const char* vrs_status_string(int code) {
@@ -300,19 +320,8 @@ int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fove
                   const vrs_params* p, const void* proj, const uint32_t* counts, uint64_t* keys, uint32_t* gids,
                   size_t capacity, uint32_t* n_inst_dev, void* ws, size_t ws_bytes, int32_t* status_dev,
                   vrs_stream_t stream) {
-    int rc = check_gaussians(g);
-    if (rc != VRS_OK) return rc;
-    Layout L;
-    rc = make_layout(cams, foveas, n_views, p, L);
-    if (rc != VRS_OK) return rc;
-    const size_t nv = size_t(n_views) * size_t(g->n);
-    if (!n_inst_dev || (nv > 0 && (!counts || !ws || !proj)) || (capacity > 0 && (!keys || !gids)))
-        return VRS_ERR_INVALID_ARG;
-    if (capacity > 0xFFFFFFFFull || nv > 0xFFFFFFFFull) return VRS_ERR_UNSUPPORTED;
-    if (ws_bytes < dup_ws_bytes(nv) || !aligned(keys, 8) || !aligned(ws, 16) || !aligned(proj, 16))
-        return VRS_ERR_INVALID_ARG;
-    return launch_duplicate(gauss_ptrs(g), geo_views(cams, L, p), knobs(p), static_cast<const float*>(proj), counts,
-                            keys, gids, capacity, n_inst_dev, ws, status_dev, reinterpret_cast<hipStream_t>(stream));
+    return duplicate_impl(g, cams, foveas, n_views, p, proj, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
+                          status_dev, stream, true);
 }
 
 size_t vrs_sort_pairs_workspace_size(size_t capacity) { return sort_ws_bytes(capacity); }
@@ -343,14 +352,15 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
     if (rc != VRS_OK) return rc;
     if (!ranges && L.tiles_total > 0) return VRS_ERR_INVALID_ARG;
     if (capacity > 0 && ws_bytes < sort_ws_bytes(capacity)) return VRS_ERR_INVALID_ARG;
-    rc = vrs_duplicate(g, cams, foveas, n_views, p, proj, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
-                       status_dev, stream);
+    // The sort's first kernel counts the kept instances into n_inst_dev[1].
+    rc = duplicate_impl(g, cams, foveas, n_views, p, proj, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
+                        status_dev, stream, false);
     if (rc != VRS_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (capacity > 0) {
         // The first pass drops the dead keys of culled candidates.
         rc = launch_sort_pairs_ex(keys, gids, n_inst_dev, n_inst_dev + 1, true, capacity,
-                                  key_bits_for(L.tiles_total), ws, status_dev, s);
+                                  key_bits_for(L.tiles_total), ws, status_dev, s, n_inst_dev + 1);
         if (rc != VRS_OK) return rc;
     }
     return launch_tile_ranges(keys, n_inst_dev + 1, capacity, L.tiles_total, ranges, s);

@@ -251,9 +251,11 @@ int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn
     return launch_status(hipGetLastError());
 }
 
+// With count_live false n_inst[1] is left at zero for the caller to fill
+// (the sort's first kernel counts the live keys anyway).
 int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn, const float* proj,
                      const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
-                     uint32_t* n_inst, void* ws, int* status, hipStream_t s) {
+                     uint32_t* n_inst, void* ws, int* status, hipStream_t s, bool count_live) {
     (void)kn;
     const size_t nslots = size_t(g.n) * size_t(views.n);
     uint32_t* offsets = static_cast<uint32_t*>(ws);
@@ -267,7 +269,7 @@ int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn,
     const size_t blocks = (nslots + 63) / 64;
     hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(64), 0, s, views, g.n, tgeo, offsets, counts, nslots,
                        n_inst, keys, gids, capacity);
-    hipLaunchKernelGGL(k_count_live, dim3(256), dim3(256), 0, s, keys, n_inst, capacity);
+    if (count_live) hipLaunchKernelGGL(k_count_live, dim3(256), dim3(256), 0, s, keys, n_inst, capacity);
     return launch_status(hipGetLastError());
 }
 

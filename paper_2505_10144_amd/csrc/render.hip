@@ -24,8 +24,6 @@
 
 namespace vrs {
 
-size_t sort_ws_bytes(size_t capacity);
-int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, int*, hipStream_t);
 int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 
 constexpr int kRenderThreads = 256;
@@ -575,14 +573,14 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
 // Longest-first order of the work items (list scheduling: the blocks that
 // take longest start first, so they do not extend the end of the launch).
 // The cost of an item is the length of its sort tile's list; the key is
-// that length on a log scale with 16 steps per octave, descending, so one
-// 8-bit radix pass orders the items (stably: equal keys keep plan order).
-__global__ void __launch_bounds__(256) k_item_keys(const uint32_t* __restrict__ items, uint32_t n,
-                                                   const uint32_t* __restrict__ ranges, RenderViews views,
-                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t it = items[i];
+// that length on a log scale with 16 steps per octave.  One block does a
+// counting sort by that key, longest first: an LDS histogram, its scan,
+// then every item takes the next slot of its key's run with an LDS atomic.
+// The order within a run depends on timing, which does not matter: every
+// item writes only its own pixels.
+constexpr int kOrderThreads = 1024;
+
+__device__ inline uint32_t item_cost_key(uint32_t it, const uint32_t* __restrict__ ranges, const RenderViews& views) {
     const RenderView& V = views.v[item_view(it)];
     const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + item_tile(it)];
     const uint32_t c = rg.y - rg.x;
@@ -592,15 +590,53 @@ __global__ void __launch_bounds__(256) k_item_keys(const uint32_t* __restrict__ 
         const uint32_t m = e >= 4 ? (c >> (e - 4)) & 15u : (c << (4 - e)) & 15u;
         b = min(255u, uint32_t(e) * 16u + m + 1u);
     }
-    keys[i] = uint64_t(255u - b);
-    vals[i] = it;
+    return 255u - b;  // ascending key = descending cost
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* __restrict__ items,
+                                                               const uint32_t* __restrict__ count_dev,
+                                                               uint32_t n_max, const uint32_t* __restrict__ ranges,
+                                                               RenderViews views, uint32_t* __restrict__ out) {
+    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x;
+    const uint32_t n = min(*count_dev, n_max);
+    if (t < 256) cnt[t] = 0;
+    __syncthreads();
+    for (uint32_t i = uint32_t(t); i < n; i += kOrderThreads)
+        atomicAdd(&cnt[item_cost_key(items[i], ranges, views)], 1u);
+    __syncthreads();
+    // Exclusive scan of the 256 counts by the first four waves.
+    uint32_t x = 0, v = 0;
+    if (t < 256) {
+        x = cnt[t];
+        v = x;
+        const int lane = t & 63;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(v, o);
+            if (lane >= o) v += y;
+        }
+        if (lane == 63) wsum[t >> 6] = v;
+    }
+    __syncthreads();
+    if (t < 256) {
+        uint32_t pre = 0;
+        for (int k = 0; k < (t >> 6); ++k) pre += wsum[k];
+        cnt[t] = pre + v - x;
+    }
+    __syncthreads();
+    for (uint32_t i = uint32_t(t); i < n; i += kOrderThreads) {
+        const uint32_t it = items[i];
+        out[atomicAdd(&cnt[item_cost_key(it, ranges, views)], 1u)] = it;
+    }
 }
 
 // Ordering area: [0, 256) the persistent schedule's unit counter, then the
-// keys, the ordered items and the radix-sort scratch.
+// ordered items.
 size_t order_ws_bytes(size_t items_max) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    return 256 + al(items_max * 8) + al(items_max * 4) + al(sort_ws_bytes(items_max));
+    return 256 + al(items_max * 4);
 }
 
 uint32_t* order_counter(void* ws) { return static_cast<uint32_t*>(ws); }
@@ -609,15 +645,14 @@ uint32_t* order_counter(void* ws) { return static_cast<uint32_t*>(ws); }
 const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, const uint32_t* count_dev,
                                    size_t items_max, const uint32_t* ranges, const RenderViews& views, void* ws,
                                    int* err, hipStream_t s) {
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    char* base = static_cast<char*>(ws) + 256;
-    uint64_t* keys = reinterpret_cast<uint64_t*>(base);
-    uint32_t* vals = reinterpret_cast<uint32_t*>(base + al(items_max * 8));
-    void* sws = base + al(items_max * 8) + al(items_max * 4);
-    hipLaunchKernelGGL(k_item_keys, dim3((n_items + 255) / 256), dim3(256), 0, s, items, n_items, ranges, views,
-                       keys, vals);
-    if (launch_sort_pairs(keys, vals, count_dev, n_items, 8, sws, err, s) != VRS_OK) return nullptr;
-    return vals;
+    (void)err;
+    (void)items_max;
+    uint32_t* out = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + 256);
+    if (n_items == 0) return out;
+    hipLaunchKernelGGL(k_order_items, dim3(1), dim3(kOrderThreads), 0, s, items, count_dev, n_items, ranges, views,
+                       out);
+    if (hipGetLastError() != hipSuccess) return nullptr;
+    return out;
 }
 
 int launch_compose(const RenderViews& views, const uint8_t* cls, hipStream_t s) {

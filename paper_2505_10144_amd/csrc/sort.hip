@@ -168,7 +168,7 @@ __device__ inline uint64_t lanemask_lt() {
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, size_t capacity, int shift, int drop,
-    const uint32_t* __restrict__ hist, int nblocks) {
+    const uint32_t* __restrict__ hist, int sd, int sb) {
     __shared__ uint32_t wcnt[kSortWaves][kRadix];
     __shared__ uint32_t goff[kRadix];     // global offset of each digit's run
     __shared__ uint32_t loff[kRadix];     // start of each digit's run in the block
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const int w = t >> 6;
     const int lane = t & 63;
     for (int k = 0; k < kSortWaves; ++k) wcnt[k][t] = 0;
-    goff[t] = hist[size_t(t) * nblocks + blockIdx.x];
+    goff[t] = hist[size_t(t) * sd + size_t(blockIdx.x) * sb];
     __syncthreads();
     const size_t n = n_eff(n_dev, capacity);
     if (size_t(blockIdx.x) * kSortTile >= n) return;  // whole block empty (uniform)
@@ -252,21 +252,35 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
 __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* __restrict__ keys,
                                                                const uint32_t* __restrict__ n_dev, size_t capacity,
                                                                int passes, int drop,
-                                                               uint32_t* __restrict__ counts, int nblocks) {
+                                                               uint32_t* __restrict__ counts, int nblocks,
+                                                               uint32_t* __restrict__ live_out) {
     __shared__ uint32_t cnt[kMaxPasses][kRadix];
+    __shared__ uint32_t wlive[kSortWaves];
     for (int p = 0; p < kMaxPasses; ++p) cnt[p][threadIdx.x] = 0;
     __syncthreads();
     const size_t n = n_eff(n_dev, capacity);
     const size_t base = size_t(blockIdx.x) * kSortTile;
+    uint32_t live = 0;
     for (int k = 0; k < kSortItemsPerLane; ++k) {
         const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
         if (idx < n) {
             const uint64_t key = keys[idx];
-            if (!(drop && key == kDeadKey))
+            if (!(drop && key == kDeadKey)) {
+                ++live;
                 for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][uint32_t(key >> (8 * p)) & 0xFFu], 1u);
+            }
         }
     }
+    if (live_out) {  // uniform
+        for (int off = 32; off >= 1; off >>= 1) live += __shfl_xor(live, off);
+        if ((threadIdx.x & 63) == 0) wlive[threadIdx.x >> 6] = live;
+    }
     __syncthreads();
+    if (live_out && threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int w = 0; w < kSortWaves; ++w) b += wlive[w];
+        if (b) atomicAdd(live_out, b);
+    }
     for (int p = 0; p < passes; ++p)
         counts[(size_t(p) * nblocks + blockIdx.x) * kRadix + threadIdx.x] = cnt[p][threadIdx.x];
 }
@@ -286,27 +300,28 @@ __global__ void __launch_bounds__(256) k_digit_totals(const uint32_t* __restrict
 // One block per digit d: exclusive scan of the digit's per-block counts,
 // plus the digit's offset (the totals of the smaller digits), in place.
 __global__ void __launch_bounds__(kScanThreads) k_digit_row_scan(uint32_t* __restrict__ hist, int nblocks,
+                                                                 int sd, int sb,
                                                                  const uint32_t* __restrict__ totals) {
     __shared__ uint32_t sh[kScanThreads];
     const int d = blockIdx.x;
     uint32_t tot;
     block_exclusive_scan(int(threadIdx.x) < d ? totals[threadIdx.x] : 0u, sh, tot);
     uint32_t carry = tot;  // sum of the totals of digits < d
-    uint32_t* row = hist + size_t(d) * nblocks;
+    uint32_t* row = hist + size_t(d) * sd;
     for (int c0 = 0; c0 < nblocks; c0 += kScanTile) {
         const int base = c0 + int(threadIdx.x) * kScanItems;
         uint32_t v[kScanItems];
         uint32_t sum = 0;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            v[k] = base + k < nblocks ? row[base + k] : 0u;
+            v[k] = base + k < nblocks ? row[size_t(base + k) * sb] : 0u;
             sum += v[k];
         }
         uint32_t t2;
         uint32_t ex = block_exclusive_scan(sum, sh, t2) + carry;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
-            if (base + k < nblocks) row[base + k] = ex;
+            if (base + k < nblocks) row[size_t(base + k) * sb] = ex;
             ex += v[k];
         }
         carry += t2;
@@ -363,8 +378,12 @@ int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
 
 // Sort min(*n_first, capacity) pairs; with drop_first the first pass drops
 // dead keys and the remaining passes sort min(*n_rest, capacity) pairs.
+// With drop_first and a non-null `live_out` (zeroed by the caller), the
+// number of live keys is added to *live_out before the first pass, so
+// n_rest may point at it.
 int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first, const uint32_t* n_rest,
-                         bool drop_first, size_t capacity, int key_bits, void* ws, int* err, hipStream_t s) {
+                         bool drop_first, size_t capacity, int key_bits, void* ws, int* err, hipStream_t s,
+                         uint32_t* live_out) {
     (void)err;  // no pass waits on another block, so nothing can time out
     if (capacity == 0 || key_bits <= 0) return VRS_OK;
     const int nb = int(sort_blocks(capacity));
@@ -380,7 +399,7 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
     // Digit totals of every pass (the live keys are the same in every pass;
     // the first pass drops the dead ones).
     hipLaunchKernelGGL(k_digit_counts, dim3(nb), dim3(kSortThreads), 0, s, keys, n_first, capacity, passes,
-                       drop_first ? 1 : 0, counts, nb);
+                       drop_first ? 1 : 0, counts, nb, drop_first ? live_out : nullptr);
     hipLaunchKernelGGL(k_digit_totals, dim3(kRadix / 4, passes), dim3(256), 0, s, counts, nb, totals);
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
@@ -388,11 +407,23 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
         const int shift = 8 * p;
         const int drop = (p == 0 && drop_first) ? 1 : 0;
         const uint32_t* n_dev = (p == 0 || !drop_first) ? n_first : n_rest;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n_dev, capacity, shift, drop, hist,
-                           nb);
-        hipLaunchKernelGGL(k_digit_row_scan, dim3(kRadix), dim3(kScanThreads), 0, s, hist, nb, totals + p * kRadix);
+        // The first pass's per-block counts are those of k_digit_counts
+        // (same keys, same order), read in place: element (digit d, block b)
+        // at d * sd + b * sb.
+        uint32_t* h = hist;
+        int sd = nb, sb = 1;
+        if (p == 0) {
+            h = counts;
+            sd = 1;
+            sb = kRadix;
+        } else {
+            hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n_dev, capacity, shift, drop,
+                               hist, nb);
+        }
+        hipLaunchKernelGGL(k_digit_row_scan, dim3(kRadix), dim3(kScanThreads), 0, s, h, nb, sd, sb,
+                           totals + p * kRadix);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, va, kb, vb, n_dev, capacity,
-                           shift, drop, hist, nb);
+                           shift, drop, h, sd, sb);
         uint64_t* tk = ka; ka = kb; kb = tk;
         uint32_t* tv = va; va = vb; vb = tv;
     }
@@ -406,7 +437,7 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
 
 int launch_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity, int key_bits,
                       void* ws, int* err, hipStream_t s) {
-    return launch_sort_pairs_ex(keys, vals, n_dev, n_dev, false, capacity, key_bits, ws, err, s);
+    return launch_sort_pairs_ex(keys, vals, n_dev, n_dev, false, capacity, key_bits, ws, err, s, nullptr);
 }
 
 int launch_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity, uint32_t tiles_total,
