@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--batch-only", action="store_true", help="run only the batched multi-view leg")
     ap.add_argument("--batch-knobs", default=None,
                     help="tile,window,blend_batch,schedule for the batch leg instead of the autotuner's choice")
+    ap.add_argument("--no-unpruned", action="store_true", help="skip the 3M-Gaussian yaw-arc leg")
+    ap.add_argument("--unpruned-only", action="store_true", help="run only the 3M-Gaussian yaw-arc leg")
     ap.add_argument("--cpu-tiles", type=int, default=24, help="32x32 tiles per eye in the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -177,6 +179,46 @@ def diff_leg(steps, warmup):
             "n_gaussians": scene.n, "views": V}
 
 
+def unpruned_leg(reps=10, warmup=2, frames=30):
+    """The unpruned-scale workload: 3M cluster Gaussians (smaller and fainter
+    than the stereo workload's), stereo 2064x2208 foveated, W=16, along a
+    30-frame +-20 degree head-yaw arc.  Per frame a renderer for that frame's
+    cameras is set up (untimed), `warmup` frames run, then `reps` frames are
+    timed one by one with HIP events; the frame's time is their median.
+    Reports the mean, p50 and p99 over the frames."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2505_10144_amd.render import Renderer, upload
+    scene, _, _, _ = synth.config_unpruned(0, frame=0)
+    g = upload(scene)
+    stream = torch.cuda.current_stream()
+    per, inst = [], []
+    for k in range(frames):
+        _, cams, fovs, params = synth.config_unpruned(0, frame=k, n=16)  # this frame's cameras
+        r = Renderer(cams, fovs, params, scene.n)
+        r.ensure_capacity(g)
+        for _ in range(warmup):
+            r.render(g)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            r.render(g)
+            b.record(stream)
+        torch.cuda.synchronize()
+        inst.append(r.check())
+        per.append(float(np.median([a.elapsed_time(b) for a, b in ev])))
+        del r
+    torch.cuda.empty_cache()
+    t = np.array(per)
+    return {"ms_mean": round(float(t.mean()), 4), "ms_p50": round(float(np.percentile(t, 50)), 4),
+            "ms_p99": round(float(np.percentile(t, 99)), 4), "fps_mean": round(1000.0 / float(t.mean()), 2),
+            "frames": frames, "reps": reps, "instances_mean": int(np.mean(inst)),
+            "workload": "unpruned: 3M cluster Gaussians (log-scale N(-5.5,0.8), opacity logit N(-1,1.5)), "
+                        "2 eyes 2064x2208, 110 deg FoV, 15 deg fovea, W=16, head yaw -20..20 deg over 30 frames",
+            "n_gaussians": scene.n}
+
+
 def batch_leg(steps, log=None, knobs=None):
     """The batched multi-view form: 1M cluster Gaussians rendered to 16 views
     of mixed size (4 each of 512^2, 1024^2, 1920x1080, 2064x2208) and FoV, a
@@ -238,6 +280,9 @@ def main():
     torch.cuda.set_device(0)
     if args.diff_only:
         print(json.dumps({"fwd_bwd": diff_leg(args.diff_steps, 3)}), flush=True)
+        return
+    if args.unpruned_only:
+        print(json.dumps({"unpruned": unpruned_leg()}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"batch": batch_leg(5, log=lambda row: print(row, file=sys.stderr, flush=True),
@@ -319,6 +364,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batch:
         out["batch"] = batch_leg(5, knobs=args.batch_knobs)
+    if not args.no_unpruned:
+        out["unpruned"] = unpruned_leg()
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, cams, fovs, params, n_items, args.cpu_tiles)
