@@ -579,6 +579,7 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
 // The order within a run depends on timing, which does not matter: every
 // item writes only its own pixels.
 constexpr int kOrderThreads = 1024;
+constexpr int kOrderPer = 8;  // items a thread has in flight
 
 __device__ inline uint32_t item_cost_key(uint32_t it, const uint32_t* __restrict__ ranges, const RenderViews& views) {
     const RenderView& V = views.v[item_view(it)];
@@ -603,8 +604,19 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
     const uint32_t n = min(*count_dev, n_max);
     if (t < 256) cnt[t] = 0;
     __syncthreads();
-    for (uint32_t i = uint32_t(t); i < n; i += kOrderThreads)
-        atomicAdd(&cnt[item_cost_key(items[i], ranges, views)], 1u);
+    // Each thread keeps kOrderPer items (and their list-range loads) in
+    // flight at a time.
+    for (uint32_t c0 = 0; c0 < n; c0 += uint32_t(kOrderThreads * kOrderPer)) {
+        uint32_t it[kOrderPer];
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j) {
+            const uint32_t i = c0 + uint32_t(j * kOrderThreads + t);
+            it[j] = i < n ? items[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j)
+            if (c0 + uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[item_cost_key(it[j], ranges, views)], 1u);
+    }
     __syncthreads();
     // Exclusive scan of the 256 counts by the first four waves.
     uint32_t x = 0, v = 0;
@@ -626,9 +638,17 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
         cnt[t] = pre + v - x;
     }
     __syncthreads();
-    for (uint32_t i = uint32_t(t); i < n; i += kOrderThreads) {
-        const uint32_t it = items[i];
-        out[atomicAdd(&cnt[item_cost_key(it, ranges, views)], 1u)] = it;
+    for (uint32_t c0 = 0; c0 < n; c0 += uint32_t(kOrderThreads * kOrderPer)) {
+        uint32_t it[kOrderPer];
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j) {
+            const uint32_t i = c0 + uint32_t(j * kOrderThreads + t);
+            it[j] = i < n ? items[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j)
+            if (c0 + uint32_t(j * kOrderThreads + t) < n)
+                out[atomicAdd(&cnt[item_cost_key(it[j], ranges, views)], 1u)] = it[j];
     }
 }
 
