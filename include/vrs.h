@@ -133,7 +133,7 @@ typedef struct {
 typedef struct {
     size_t proj_bytes;       /* per view and Gaussian: a 128-byte FP32 render record
                                 ([n_views][n][32] floats); after all of them a
-                                224-byte FP64 tile-test record each; after those a
+                                192-byte FP64 tile-test record each; after those a
                                 float4 colour (r, g, b, 0) each                      */
     size_t counts_bytes;     /* uint32 counts[n_views][n]                         */
     uint32_t tiles_total;    /* sum over views of sort-grid tiles (ranges rows)    */

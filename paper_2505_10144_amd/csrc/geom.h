@@ -50,11 +50,10 @@ __device__ inline GaussLocal load_gaussian(const GaussPtrs& g, int i) {
     return L;
 }
 
-// What K3 needs of one Gaussian in one view, stored by K1 (224 bytes).
+// What K3 needs of one Gaussian in one view, stored by K1 (192 bytes).
 struct TileGeo {
     double x0, y0;     // image point of the mean (pixels)
     double M[4];       // whitened tangent coords z = M delta / h, |z|^2 = D^2
-    double Minv[4];
     double a3x, a3y;   // h = 1 + a3 . delta  (> 0 iff the ray is in front)
     double kappa;      // keep iff D^2_min <= kappa = 2 ln(opacity / alpha_min)
     double r;          // |mu_c|: the depth when the mean lies in the tile
@@ -127,11 +126,6 @@ __device__ inline bool make_geo(const GaussLocal& G, const GeoView& V, const Kno
     t.M[1] = uz * (l00 * A01 + l01 * A11);
     t.M[2] = uz * (l11 * A10);
     t.M[3] = uz * (l11 * A11);
-    const double inv_md = 1.0 / (t.M[0] * t.M[3] - t.M[1] * t.M[2]);
-    t.Minv[0] = t.M[3] * inv_md;
-    t.Minv[1] = -t.M[1] * inv_md;
-    t.Minv[2] = -t.M[2] * inv_md;
-    t.Minv[3] = t.M[0] * inv_md;
     t.a3x = uz * ux * inv_f;
     t.a3y = uz * uy * inv_f;
     const double inv_z = 1.0 / o.muc[2];
@@ -301,8 +295,9 @@ __device__ inline bool tile_test(const TileGeo& g, const GeoView& V, double bx0,
     }
     if (!(best <= g.kappa)) return false;
     // Back to the image: delta = v / (1 - a3 . v), v = M^-1 z.
-    const double vx = g.Minv[0] * bx + g.Minv[1] * by;
-    const double vy = g.Minv[2] * bx + g.Minv[3] * by;
+    const double inv_md = 1.0 / (g.M[0] * g.M[3] - g.M[1] * g.M[2]);
+    const double vx = (g.M[3] * inv_md) * bx + (-g.M[1] * inv_md) * by;
+    const double vy = (-g.M[2] * inv_md) * bx + (g.M[0] * inv_md) * by;
     const double s = 1.0 / (1.0 - (g.a3x * vx + g.a3y * vy));
     const double ddx = vx * s, ddy = vy * s;
     const double w0 = g.w0[0] + ddx * g.wx[0] + ddy * g.wy[0];

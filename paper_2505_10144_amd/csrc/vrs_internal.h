@@ -34,9 +34,9 @@ enum RecField : int {
 };
 
 // Layout of the `proj` buffer for nslots = n_views * n (view-major) slots:
-// the FP32 render records, then the FP64 tile-test records (224 bytes
+// the FP32 render records, then the FP64 tile-test records (192 bytes
 // each), then one float4 colour (r, g, b, 0) per slot.
-constexpr size_t kTileGeoBytes = 224;
+constexpr size_t kTileGeoBytes = 192;
 __host__ __device__ inline size_t tgeo_offset_bytes(size_t nslots) { return nslots * kRec * sizeof(float); }
 __host__ __device__ inline size_t colour_offset_bytes(size_t nslots) {
     return nslots * (kRec * sizeof(float) + kTileGeoBytes);
