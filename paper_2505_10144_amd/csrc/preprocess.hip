@@ -90,12 +90,11 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
 // View-dependent colour of every Gaussian in every view from its SH
 // coefficients, written to the colour array as one float4 per slot (kept
 // apart from k_preprocess so that the 48 coefficients do not occupy
-// registers across the FP64 set-up).  Views go in groups of four:
-// each coefficient is read once per group and applied to all of its views,
-// so a stereo pair reads the coefficients from HBM once.  Culled
-// Gaussian-views get a colour too; no list refers to them.
-constexpr int kColorViews = 4;
-
+// registers across the FP64 set-up).  Views go in groups (two for a
+// stereo pair, else four): each coefficient is read once per group and
+// applied to all of its views, so a stereo pair reads the coefficients from
+// HBM once.  Culled Gaussian-views get a colour too; no list refers to them.
+template <int kColorViews>
 __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, float* __restrict__ proj) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
@@ -247,7 +246,12 @@ int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn
     TileGeo* tgeo = reinterpret_cast<TileGeo*>(reinterpret_cast<char*>(proj) + tgeo_offset_bytes(nslots));
     const int blocks = (g.n + 255) / 256;
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, s, g, views, kn, proj, tgeo, counts);
-    hipLaunchKernelGGL(k_color, dim3(blocks), dim3(256), 0, s, g, views, proj);
+    // Groups of two views for a stereo pair (no work on padding views),
+    // else four.
+    if (views.n <= 2)
+        hipLaunchKernelGGL(k_color<2>, dim3(blocks), dim3(256), 0, s, g, views, proj);
+    else
+        hipLaunchKernelGGL(k_color<4>, dim3(blocks), dim3(256), 0, s, g, views, proj);
     return launch_status(hipGetLastError());
 }
 
