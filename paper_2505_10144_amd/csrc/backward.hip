@@ -169,8 +169,10 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
                                                             const uint32_t* __restrict__ ranges, BwdViews views,
                                                             Knobs kn, float* __restrict__ grad2d) {
     __shared__ float4 ring[kRing][6];
-    __shared__ unsigned long long acc[kRing][kG];
-    __shared__ int acc_scale[kRing][kG];
+    // Value-major, so that the lanes of one atomic instruction (one value of
+    // different entries) fall in different banks.
+    __shared__ unsigned long long acc[kG][kRing];
+    __shared__ int acc_scale[kG][kRing];
     __shared__ float4 queue[kBwdThreads / 64][kQueue];
 
     const uint32_t item = blockIdx.x;
@@ -344,7 +346,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
 #pragma unroll
             for (int k = 0; k < kG; ++k) {
                 if (g[k] == 0.f) continue;
-                if (!in_ring || !fixed_add(&acc[sl][k], &acc_scale[sl][k], g[k])) unsafeAtomicAdd(dst + k, g[k]);
+                if (!in_ring || !fixed_add(&acc[k][sl], &acc_scale[k][sl], g[k])) unsafeAtomicAdd(dst + k, g[k]);
             }
         }
         qhead += nq;
@@ -394,10 +396,10 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             // Flush the batch that leaves the ring.
             for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
                 const int s = base + w / kG, k = w % kG;
-                const int sc = acc_scale[s][k];
-                if (sc != kUnset && acc[s][k] != 0ull)
+                const int sc = acc_scale[k][s];
+                if (sc != kUnset && acc[k][s] != 0ull)
                     unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[s][5].z)) * kG + k],
-                                    fixed_value(acc[s][k], sc));
+                                    fixed_value(acc[k][s], sc));
             }
             __syncthreads();
             ring_lo = b0 + kBwdBatch - kRing;
@@ -410,8 +412,8 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             for (int k = 0; k < 6; ++k) ring[base + t][k] = e[k];
         }
         for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
-            acc[base + w / kG][w % kG] = 0ull;
-            acc_scale[base + w / kG][w % kG] = kUnset;
+            acc[w % kG][base + w / kG] = 0ull;
+            acc_scale[w % kG][base + w / kG] = kUnset;
         }
         last_b0 = b0;
         staged_end = b0 + uint32_t(nb);
@@ -475,9 +477,9 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         const int s = w / kG, k = w % kG;
         const uint32_t a = first + (uint32_t(s) + uint32_t(kRing) - first % uint32_t(kRing)) % uint32_t(kRing);
         if (a >= staged_end) continue;
-        const int sc = acc_scale[s][k];
-        if (sc != kUnset && acc[s][k] != 0ull)
-            unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[s][5].z)) * kG + k], fixed_value(acc[s][k], sc));
+        const int sc = acc_scale[k][s];
+        if (sc != kUnset && acc[k][s] != 0ull)
+            unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[s][5].z)) * kG + k], fixed_value(acc[k][s], sc));
     }
 }
 
