@@ -105,7 +105,8 @@ typedef struct {
 /* Blend schedules (performance only; the output is identical). */
 #define VRS_SCHEDULE_ONESHOT 0    /* one block per work item, longest first        */
 #define VRS_SCHEDULE_PERSISTENT 1 /* a chip-filling grid whose waves draw (item,    \
-                                     row) units longest first from an atomic counter */
+                                     quadrant) units longest first from an atomic
+                                     counter                                        */
 
 /* Renderer knobs.  tile: 16 or 32 for plain views (a 32x32 tile is rendered
  * as four 16x16 subtiles) -- foveated views always use 32x32 sort tiles;

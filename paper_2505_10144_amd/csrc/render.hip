@@ -129,8 +129,11 @@ __device__ inline void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wave's share of a work item: rows 4 wv .. 4 wv + 3 of a 16x16 (sub)tile,
-// or rows 8 wv .. 8 wv + 7 of a LOW tile's half-resolution samples.  `st` is
+// One wave's share of a work item: the 8x8 quadrant wv of the item's 16x16
+// samples (pixels of a 16x16 (sub)tile, or the half-resolution samples of a
+// LOW tile).  A square quadrant rather than a 16x4 strip: its pixel box
+// meets fewer splat boxes, and its samples see more similar lists, so the
+// insertion network idles less (blend 0.70 -> 0.66 ms).  `st` is
 // the wave's own LDS slice; `batch` (<= kBatch) list entries are staged at a
 // time.  STATS = true is the instrumented variant: it also counts evaluated
 // (sample, entry) pairs, pairs that reach alpha_min, in-image samples,
@@ -163,21 +166,23 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     const int T = V.foveated ? 32 : V.T;
     const int tx = int(tile % uint32_t(V.ntx)), ty = int(tile / uint32_t(V.ntx));
     const int ox = tx * T, oy = ty * T;  // sort-tile origin (pixels)
-    const int lane = int(threadIdx.x) & 63, t = wv * 64 + lane;
+    const int lane = int(threadIdx.x) & 63;
 
     // Sample of this thread, relative to the tile origin.
     int px, py;      // first pixel covered
     float sx, sy;    // sample position relative to (ox, oy)
+    // Wave wv owns the 8x8 quadrant (qx, qy) of the item's 16x16 samples.
+    const int qx = wv & 1, qy = wv >> 1;
     if (cls == VRS_CLASS_LOW) {
-        const int gx = t & 15, gy = t >> 4;
+        const int gx = 8 * qx + (lane & 7), gy = 8 * qy + (lane >> 3);
         px = ox + 2 * gx;
         py = oy + 2 * gy;
         sx = float(2 * gx + 1);
         sy = float(2 * gy + 1);
     } else {
         // Quad-major layout: lanes 4q..4q+3 hold one aligned 2x2 group.
-        const int q = t >> 2, k = t & 3;
-        const int lx = 2 * (q & 7) + (k & 1), ly = 2 * (q >> 3) + (k >> 1);
+        const int q = lane >> 2, k = lane & 3;
+        const int lx = 8 * qx + 2 * (q & 3) + (k & 1), ly = 8 * qy + 2 * (q >> 2) + (k >> 1);
         const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
         px = ox + bx + lx;
         py = oy + by + ly;
@@ -199,7 +204,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     uint32_t n_pairs = 0, n_contrib = 0, n_staged = 0, n_push = 0;
     int cnt = 0;  // entries in this lane's inbox
     float pw = 0.f;                                 // weight of the last emission
-    float4 pc = make_float4(0.f, 0.f, 0.f, 0.f);   // its colour (y, z, w)
+    float4 pc = make_float4(0.f, 0.f, 0.f, 0.f);   // its colour (x, y, z)
 
     // This wave's samples lie in a pixel rectangle; list entries whose box
     // misses it cannot reach alpha_min at any of them and are skipped for
@@ -207,12 +212,12 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     // parent's 32x32 list, generalised to every wave).
     float rx0, ry0, rx1, ry1;
     if (cls == VRS_CLASS_LOW) {
-        rx0 = float(ox + 1); rx1 = float(ox + 31);
-        ry0 = float(oy + 8 * wv + 1); ry1 = float(oy + 8 * wv + 7);
+        rx0 = float(ox + 16 * qx + 1); rx1 = float(ox + 16 * qx + 15);
+        ry0 = float(oy + 16 * qy + 1); ry1 = float(oy + 16 * qy + 15);
     } else {
         const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
-        rx0 = float(ox + bx) + 0.5f; rx1 = float(ox + bx) + 15.5f;
-        ry0 = float(oy + by + 4 * wv) + 0.5f; ry1 = float(oy + by + 4 * wv) + 3.5f;
+        rx0 = float(ox + bx + 8 * qx) + 0.5f; rx1 = float(ox + bx + 8 * qx) + 7.5f;
+        ry0 = float(oy + by + 8 * qy) + 0.5f; ry1 = float(oy + by + 8 * qy) + 7.5f;
     }
 
     // Collect entries into the inboxes until some lane's inbox is full or the
@@ -411,7 +416,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
 
 // K6 launch.  One-shot schedule (PERSIST = false): one block per work item,
 // in the given (longest-first) order.  Persistent schedule: a grid that
-// fills the chip once, whose waves take (item, wave row) units in order from
+// fills the chip once, whose waves take (item, quadrant) units in order from
 // an atomic counter until none are left, so a wave that finishes early
 // starts new work at once instead of idling until its block's slowest wave
 // ends.  The counter must be zero at launch; every wave exits after drawing
