@@ -188,11 +188,13 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    // Sample of a lane of this wave: the forward's quad-major 16x16 layout.
+    // Sample of a lane of this wave: as in the forward, wave wv owns the 8x8
+    // quadrant (qx, qy) of the 16x16 samples, lanes 4q..4q+3 a 2x2 group.
     const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
+    const int qx = wv & 1, qy = wv >> 1;
     auto sample_of = [&](int l, float& sx_, float& sy_, int& px_, int& py_) {
-        const int tt = wv * 64 + l, qd = tt >> 2, kq = tt & 3;
-        const int lx = 2 * (qd & 7) + (kq & 1), ly = 2 * (qd >> 3) + (kq >> 1);
+        const int qd = l >> 2, kq = l & 3;
+        const int lx = 8 * qx + 2 * (qd & 3) + (kq & 1), ly = 8 * qy + 2 * (qd >> 2) + (kq >> 1);
         px_ = ox + bx + lx;
         py_ = oy + by + ly;
         sx_ = float(bx + lx) + 0.5f;
@@ -230,8 +232,8 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
     const float4* vcol = colour_array(proj, size_t(views.n) * size_t(n_gauss)) + size_t(v) * size_t(n_gauss);
     float* vgrad = grad2d + size_t(v) * size_t(n_gauss) * kG;
-    const float rx0 = float(ox + bx) + 0.5f, rx1 = float(ox + bx) + 15.5f;
-    const float ry0 = float(oy + by + 4 * wv) + 0.5f, ry1 = float(oy + by + 4 * wv) + 3.5f;
+    const float rx0 = float(ox + bx + 8 * qx) + 0.5f, rx1 = float(ox + bx + 8 * qx) + 7.5f;
+    const float ry0 = float(oy + by + 8 * qy) + 0.5f, ry1 = float(oy + by + 8 * qy) + 7.5f;
     uint32_t ring_lo = 0;  // smallest arrival index whose record is still in the ring
 
     // An emission (a blended (sample, entry) pair) is completed in three
