@@ -648,17 +648,20 @@ __device__ inline Grad3 sh_basis_grad(int k, float x, float y, float z) {
 // d = mean - eye centre: dL/dsh_kc = g_c Y_k(u) where the colour is not
 // clamped, and dL/dmean = J_u^T sum_c g_c grad Y . sh_c with
 // J_u = (I - u u^T) / |d|.  One thread per Gaussian; writes out.sh and
-// out.means (the geometry part adds to the latter).
+// out.means (the geometry part adds to the latter).  The SH degree is a
+// template parameter: no per-coefficient branches, and the loads of a view
+// can be issued together.
+template <int kDeg>
 __global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, const float* __restrict__ grad2d,
                                                    GradPtrs out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     const int n = g.n;
-    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    constexpr int K = (kDeg + 1) * (kDeg + 1);
     const double mu[3] = {double(g.means[i]), double(g.means[n + i]), double(g.means[2 * n + i])};
-    float gsh[16][3];
+    float gsh[K][3];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
+    for (int k = 0; k < K; ++k) gsh[k][0] = gsh[k][1] = gsh[k][2] = 0.f;
     float gm[3] = {0.f, 0.f, 0.f};
     for (int v = 0; v < views.n; ++v) {
         const GeoView& V = views.v[v];
@@ -674,17 +677,15 @@ __global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, 
         // Colour values and gradients with respect to u.
         Grad3 col[3] = {g3(0.5f, 0.f, 0.f, 0.f), g3(0.5f, 0.f, 0.f, 0.f), g3(0.5f, 0.f, 0.f, 0.f)};
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (k < K) {
-                const Grad3 y = sh_basis_grad(k, u[0], u[1], u[2]);
+        for (int k = 0; k < K; ++k) {
+            const Grad3 y = sh_basis_grad(k, u[0], u[1], u[2]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float a = g.sh[(k * 3 + c) * n + i];
-                    col[c].v = fmaf(a, y.v, col[c].v);
-                    col[c].x = fmaf(a, y.x, col[c].x);
-                    col[c].y = fmaf(a, y.y, col[c].y);
-                    col[c].z = fmaf(a, y.z, col[c].z);
-                }
+            for (int c = 0; c < 3; ++c) {
+                const float a = g.sh[(k * 3 + c) * n + i];
+                col[c].v = fmaf(a, y.v, col[c].v);
+                col[c].x = fmaf(a, y.x, col[c].x);
+                col[c].y = fmaf(a, y.y, col[c].y);
+                col[c].z = fmaf(a, y.z, col[c].z);
             }
         }
         float wc[3], gu[3] = {0.f, 0.f, 0.f};
@@ -701,7 +702,7 @@ __global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) gm[c] = fmaf(gu[c] - gdotu * u[c], idn, gm[c]);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < K; ++k) {
             const float yv = sh_basis_grad(k, u[0], u[1], u[2]).v;
 #pragma unroll
             for (int c = 0; c < 3; ++c) gsh[k][c] = fmaf(wc[c], yv, gsh[k][c]);
@@ -710,11 +711,9 @@ __global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, 
 #pragma unroll
     for (int c = 0; c < 3; ++c) out.means[c * n + i] = gm[c];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        if (k < K) {
+    for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) out.sh[(k * 3 + c) * n + i] = gsh[k][c];
-        }
+        for (int c = 0; c < 3; ++c) out.sh[(k * 3 + c) * n + i] = gsh[k][c];
     }
 }
 
@@ -810,7 +809,13 @@ int launch_backward(const GaussPtrs& g, const GeoViews& gv, const float* proj, c
 #undef VRS_BWD_W
     }
     if (g.n > 0) {
-        hipLaunchKernelGGL(k_color_bwd, dim3(unsigned((g.n + 255) / 256)), dim3(256), 0, s, g, gv, grad2d, out);
+        const dim3 cg(unsigned((g.n + 255) / 256));
+        switch (g.sh_degree) {
+            case 0: hipLaunchKernelGGL(k_color_bwd<0>, cg, dim3(256), 0, s, g, gv, grad2d, out); break;
+            case 1: hipLaunchKernelGGL(k_color_bwd<1>, cg, dim3(256), 0, s, g, gv, grad2d, out); break;
+            case 2: hipLaunchKernelGGL(k_color_bwd<2>, cg, dim3(256), 0, s, g, gv, grad2d, out); break;
+            default: hipLaunchKernelGGL(k_color_bwd<3>, cg, dim3(256), 0, s, g, gv, grad2d, out); break;
+        }
         hipLaunchKernelGGL(k_geom_bwd, dim3(unsigned((g.n + 127) / 128)), dim3(128), 0, s, g, gv, kn, grad2d, out);
     }
     return launch_status(hipGetLastError());

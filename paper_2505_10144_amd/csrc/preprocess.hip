@@ -16,6 +16,7 @@ namespace vrs {
 // Real spherical harmonics (orthonormal, Condon-Shortley phase) up to degree
 // 3 written as polynomials of the unit direction (x, y, z), k = l^2 + l + m.
 __device__ inline void sh_basis(const float v[3], float Y[16]) {
+#pragma clang fp contract(off)
     const float x = v[0], y = v[1], z = v[2];
     constexpr double pi = M_PI;
     const float c0 = float(0.5 / sqrt(pi));
@@ -90,16 +91,26 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
 // View-dependent colour of every Gaussian in every view from its SH
 // coefficients, written to the colour array as one float4 per slot (kept
 // apart from k_preprocess so that the 48 coefficients do not occupy
-// registers across the FP64 set-up).  Views go in groups (two for a
-// stereo pair, else four): each coefficient is read once per group and
-// applied to all of its views, so a stereo pair reads the coefficients from
-// HBM once.  Culled Gaussian-views get a colour too; no list refers to them.
-template <int kColorViews>
+// registers across the FP64 set-up).  The SH degree is a template
+// parameter: the coefficients are loaded once per Gaussian, all at a time,
+// and applied to every view; views go in groups (two for a stereo pair,
+// else four) that bound the registers their basis values take.  Culled
+// Gaussian-views get a colour too; no list refers to them.
+template <int kColorViews, int kDeg>
 __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, float* __restrict__ proj) {
+    // No implicit multiply-add contraction: every rounding is the one the
+    // source states (the explicit fmaf calls), so a view's colour is the
+    // same bits whichever instantiation and view slot computes it.
+#pragma clang fp contract(off)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
     const int n = g.n;
-    const int K = (g.sh_degree + 1) * (g.sh_degree + 1);
+    constexpr int K = (kDeg + 1) * (kDeg + 1);
+    // All coefficients are loaded up front, so their loads are in flight
+    // together rather than one coefficient's three at a time.
+    float sh[K * 3];
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) sh[k] = g.sh[k * n + i];
     float4* cols = const_cast<float4*>(colour_array(proj, size_t(views.n) * size_t(n)));
     const double mu[3] = {double(g.means[i]), double(g.means[n + i]), double(g.means[2 * n + i])};
     for (int v0 = 0; v0 < views.n; v0 += kColorViews) {
@@ -119,14 +130,11 @@ __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, floa
             rgb[j][0] = rgb[j][1] = rgb[j][2] = 0.5f;
         }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (k < K) {
+        for (int k = 0; k < K; ++k) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float a = g.sh[(k * 3 + c) * n + i];
+            for (int c = 0; c < 3; ++c) {
 #pragma unroll
-                    for (int j = 0; j < kColorViews; ++j) rgb[j][c] = fmaf(a, Y[j][k], rgb[j][c]);
-                }
+                for (int j = 0; j < kColorViews; ++j) rgb[j][c] = fmaf(sh[k * 3 + c], Y[j][k], rgb[j][c]);
             }
         }
 #pragma unroll
@@ -239,6 +247,16 @@ __global__ void k_dup_init(uint32_t* n_inst, size_t capacity, int* status) {
 // Host launchers.
 // ---------------------------------------------------------------------------
 
+template <int kColorViews>
+void launch_color(const GaussPtrs& g, const GeoViews& views, float* proj, int blocks, hipStream_t s) {
+    switch (g.sh_degree) {
+        case 0: hipLaunchKernelGGL((k_color<kColorViews, 0>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
+        case 1: hipLaunchKernelGGL((k_color<kColorViews, 1>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
+        case 2: hipLaunchKernelGGL((k_color<kColorViews, 2>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
+        default: hipLaunchKernelGGL((k_color<kColorViews, 3>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
+    }
+}
+
 int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn, float* proj,
                       uint32_t* counts, hipStream_t s) {
     if (g.n == 0) return VRS_OK;
@@ -249,9 +267,9 @@ int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn
     // Groups of two views for a stereo pair (no work on padding views),
     // else four.
     if (views.n <= 2)
-        hipLaunchKernelGGL(k_color<2>, dim3(blocks), dim3(256), 0, s, g, views, proj);
+        launch_color<2>(g, views, proj, blocks, s);
     else
-        hipLaunchKernelGGL(k_color<4>, dim3(blocks), dim3(256), 0, s, g, views, proj);
+        launch_color<4>(g, views, proj, blocks, s);
     return launch_status(hipGetLastError());
 }
 
