@@ -30,6 +30,7 @@ constexpr int kSortTile = kSortThreads * kSortItemsPerLane;  // 2048 (twice the 
 constexpr int kRadix = 256;
 constexpr uint64_t kDeadKey = ~0ull;
 constexpr int kMaxPasses = 8;
+static_assert(kSortThreads == kRadix, "one thread per digit in the count kernels");
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of uint32 (per-block scan, scan of block sums, add-back).
@@ -253,10 +254,14 @@ __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* _
                                                                const uint32_t* __restrict__ n_dev, size_t capacity,
                                                                int passes, int drop,
                                                                uint32_t* __restrict__ counts, int nblocks,
-                                                               uint32_t* __restrict__ live_out) {
+                                                               uint32_t* __restrict__ live_out,
+                                                               uint32_t* __restrict__ totals) {
     __shared__ uint32_t cnt[kMaxPasses][kRadix];
     __shared__ uint32_t wlive[kSortWaves];
     for (int p = 0; p < kMaxPasses; ++p) cnt[p][threadIdx.x] = 0;
+    // The digit totals that k_digit_totals adds up next start at zero.
+    if (blockIdx.x == 0)
+        for (int p = 0; p < passes; ++p) totals[p * kRadix + threadIdx.x] = 0;
     __syncthreads();
     const size_t n = n_eff(n_dev, capacity);
     const size_t base = size_t(blockIdx.x) * kSortTile;
@@ -285,16 +290,20 @@ __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* _
         counts[(size_t(p) * nblocks + blockIdx.x) * kRadix + threadIdx.x] = cnt[p][threadIdx.x];
 }
 
-// Digit totals of every pass: block (p, g) sums digits 4g .. 4g+3 of pass p
-// over all tiles, 64 threads per digit.
-__global__ void __launch_bounds__(256) k_digit_totals(const uint32_t* __restrict__ counts, int nblocks,
-                                                      uint32_t* __restrict__ totals) {
-    const int p = blockIdx.y, d = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const uint32_t* c = counts + size_t(p) * nblocks * kRadix + d;
+// Digit totals of every pass: block (r, p) adds rows [32r, 32r + 32) of
+// pass p's counts, one thread per digit, so every load reads a whole
+// 1 KB row; the partial sums go to totals (zeroed by k_digit_counts) with
+// integer atomics, which are exact in any order.
+constexpr int kTotalRows = 32;
+__global__ void __launch_bounds__(kRadix) k_digit_totals(const uint32_t* __restrict__ counts, int nblocks,
+                                                         uint32_t* __restrict__ totals) {
+    const int p = blockIdx.y, d = threadIdx.x, b0 = blockIdx.x * kTotalRows;
+    const int rows = min(kTotalRows, nblocks - b0);
+    const uint32_t* c = counts + (size_t(p) * nblocks + b0) * kRadix + d;
     uint32_t tot = 0;
-    for (int b = lane; b < nblocks; b += 64) tot += c[size_t(b) * kRadix];
-    for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off);
-    if (lane == 0) totals[p * kRadix + d] = tot;
+#pragma unroll 8
+    for (int r = 0; r < rows; ++r) tot += c[size_t(r) * kRadix];
+    if (tot) atomicAdd(&totals[p * kRadix + d], tot);
 }
 
 // One block per digit d: exclusive scan of the digit's per-block counts,
@@ -399,8 +408,9 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
     // Digit totals of every pass (the live keys are the same in every pass;
     // the first pass drops the dead ones).
     hipLaunchKernelGGL(k_digit_counts, dim3(nb), dim3(kSortThreads), 0, s, keys, n_first, capacity, passes,
-                       drop_first ? 1 : 0, counts, nb, drop_first ? live_out : nullptr);
-    hipLaunchKernelGGL(k_digit_totals, dim3(kRadix / 4, passes), dim3(256), 0, s, counts, nb, totals);
+                       drop_first ? 1 : 0, counts, nb, drop_first ? live_out : nullptr, totals);
+    hipLaunchKernelGGL(k_digit_totals, dim3((nb + kTotalRows - 1) / kTotalRows, passes), dim3(kRadix), 0, s, counts,
+                       nb, totals);
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
     for (int p = 0; p < passes; ++p) {
