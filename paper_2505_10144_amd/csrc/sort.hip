@@ -249,13 +249,14 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
 }
 
 // Digit counts of every pass for one 2048-key tile: block b writes
-// counts[p][b][d].
+// counts[p][b][d], and hist0[d][b] for the first pass.
 __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* __restrict__ keys,
                                                                const uint32_t* __restrict__ n_dev, size_t capacity,
                                                                int passes, int drop,
                                                                uint32_t* __restrict__ counts, int nblocks,
                                                                uint32_t* __restrict__ live_out,
-                                                               uint32_t* __restrict__ totals) {
+                                                               uint32_t* __restrict__ totals,
+                                                               uint32_t* __restrict__ hist0) {
     __shared__ uint32_t cnt[kMaxPasses][kRadix];
     __shared__ uint32_t wlive[kSortWaves];
     for (int p = 0; p < kMaxPasses; ++p) cnt[p][threadIdx.x] = 0;
@@ -288,6 +289,9 @@ __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* _
     }
     for (int p = 0; p < passes; ++p)
         counts[(size_t(p) * nblocks + blockIdx.x) * kRadix + threadIdx.x] = cnt[p][threadIdx.x];
+    // The first pass's counts once more, digit-major as the later passes'
+    // histograms are, so that its row scan reads whole rows.
+    hist0[size_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[0][threadIdx.x];
 }
 
 // Digit totals of every pass: block (r, p) adds rows [32r, 32r + 32) of
@@ -408,7 +412,7 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
     // Digit totals of every pass (the live keys are the same in every pass;
     // the first pass drops the dead ones).
     hipLaunchKernelGGL(k_digit_counts, dim3(nb), dim3(kSortThreads), 0, s, keys, n_first, capacity, passes,
-                       drop_first ? 1 : 0, counts, nb, drop_first ? live_out : nullptr, totals);
+                       drop_first ? 1 : 0, counts, nb, drop_first ? live_out : nullptr, totals, hist);
     hipLaunchKernelGGL(k_digit_totals, dim3((nb + kTotalRows - 1) / kTotalRows, passes), dim3(kRadix), 0, s, counts,
                        nb, totals);
     uint64_t *ka = keys, *kb = k2;
@@ -417,16 +421,12 @@ int launch_sort_pairs_ex(uint64_t* keys, uint32_t* vals, const uint32_t* n_first
         const int shift = 8 * p;
         const int drop = (p == 0 && drop_first) ? 1 : 0;
         const uint32_t* n_dev = (p == 0 || !drop_first) ? n_first : n_rest;
-        // The first pass's per-block counts are those of k_digit_counts
-        // (same keys, same order), read in place: element (digit d, block b)
-        // at d * sd + b * sb.
+        // The first pass's per-block counts are those k_digit_counts wrote
+        // to hist (same keys, same order).  Element (digit d, block b) at
+        // d * sd + b * sb.
         uint32_t* h = hist;
-        int sd = nb, sb = 1;
-        if (p == 0) {
-            h = counts;
-            sd = 1;
-            sb = kRadix;
-        } else {
+        const int sd = nb, sb = 1;
+        if (p > 0) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n_dev, capacity, shift, drop,
                                hist, nb);
         }
