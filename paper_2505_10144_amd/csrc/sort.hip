@@ -39,20 +39,29 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
+// Exclusive scan over the block (kScanThreads threads): an inclusive scan
+// within each wave by lane shuffles, then the wave totals through LDS.  The
+// closing barrier lets the caller scan again with the same `sh`.
 __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* sh, uint32_t& total) {
-    const int t = threadIdx.x;
-    sh[t] = x;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const uint32_t y = t >= off ? sh[t - off] : 0u;
-        __syncthreads();
-        sh[t] += y;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t v = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(v, off);
+        if (lane >= off) v += y;
     }
-    total = sh[kScanThreads - 1];
-    const uint32_t incl = sh[t];
+    if (lane == 63) sh[w] = v;
     __syncthreads();
-    return incl - x;
+    uint32_t below = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        const uint32_t s = sh[k];
+        below += k < w ? s : 0u;
+        all += s;
+    }
+    total = all;
+    __syncthreads();
+    return below + v - x;
 }
 
 // in and out may alias: every thread reads its items before writing them.
