@@ -442,6 +442,29 @@ def test_record_colours_and_alpha(R):
         np.testing.assert_allclose(np.exp2(rec[v, ok, 10]), pre["sigma"][ok], rtol=1e-6)
 
 
+@pytest.mark.parametrize("degree", [0, 1, 2, 3])
+def test_colours_every_sh_degree(R, degree):
+    """The colour array for SH degrees 0-3 equals the oracle's SH colour,
+    through both the two-view kernel (one view) and the four-view kernel
+    (three views, one padding slot), and a view's colour has the same bits
+    in both."""
+    from oracle.render import preprocess_view
+    scene = synth.uniform_scene(11 + degree, 2000, sh_degree=degree, sh_std=0.5)
+    cams = [synth.camera_translate((0.3 * k - 0.3, 0.1 * k, -3.0), 80.0 + 10 * k, 96, 64) for k in range(3)]
+    params = synth.default_params(tile=16, window=8)
+    print(f"[colours] degree={degree} n={scene.n}", flush=True)
+    r3, _ = _stage_setup(R, scene, cams, [synth.fovea_off()] * 3, params)
+    cols3 = r3.colours().cpu().numpy()
+    r1, _ = _stage_setup(R, scene, cams[1:2], [synth.fovea_off()], params)
+    cols1 = r1.colours().cpu().numpy()
+    assert np.array_equal(cols1[0], cols3[1])
+    for v, cam in enumerate(cams):
+        pre = preprocess_view(scene, cam, params)
+        ok = pre["valid"]
+        assert ok.sum() > 100
+        np.testing.assert_allclose(cols3[v, ok, :3].astype(np.float64), pre["color"][ok], atol=2e-6)
+
+
 @pytest.mark.parametrize("scale", [(-3.5, 1.2), (-2.5, 0.5)])
 def test_record_boxes_contain_the_footprint(R, scale):
     """K1's pixel box (cone bound intersected with the exact conic footprint
