@@ -47,44 +47,67 @@ __device__ inline void sh_basis(const float v[3], float Y[16]) {
     Y[15] = -c3a * x * (x * x - 3.f * y * y);
 }
 
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The render records of a wave's 64 consecutive Gaussians are staged in LDS
+// and written out as contiguous 1 KB pieces (a record per lane would make
+// every store instruction touch 64 different lines).
 __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views, Knobs kn,
                                                     float* __restrict__ proj, TileGeo* __restrict__ tgeo,
                                                     uint32_t* __restrict__ counts) {
+    __shared__ float4 stage[4][64 * 8];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
-    const GaussLocal G = load_gaussian(g, i);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wave_i0 = i - lane;
+    if (wave_i0 >= g.n) return;  // whole wave past the end
+    const bool inb = i < g.n;
+    const GaussLocal G = load_gaussian(g, inb ? i : wave_i0);
     for (int v = 0; v < views.n; ++v) {
         const GeoView& V = views.v[v];
         const size_t slot = size_t(v) * size_t(g.n) + size_t(i);
         Geo geo;
-        if (!make_geo(G, V, kn, views.ln_amin, geo)) {
-            counts[slot] = 0;
-            continue;
+        const bool ok = inb && make_geo(G, V, kn, views.ln_amin, geo);
+        if (inb && !ok) counts[slot] = 0;
+        if (ok) {
+            int tx0, tx1, ty0, ty1;
+            float bbox[4];
+            cone_tiles(geo, V, tx0, tx1, ty0, ty1, bbox);
+            const int ncx = max(tx1 - tx0 + 1, 0), ncy = max(ty1 - ty0 + 1, 0);
+            TileGeo& t = geo.tg;
+            t.tx0 = tx0;
+            t.ty0 = ty0;
+            t.ncx = ncx;
+            t.count = ncx * ncy;
+            counts[slot] = uint32_t(ncx * ncy);
+            tgeo[slot] = t;
+            // Render record (field map in vrs_internal.h); the colour goes to
+            // the colour array (k_color).
+            const double xi = floor(t.x0), yi = floor(t.y0);
+            const float zs = float(sqrt(0.5 / M_LN2));  // |z|^2 = (log2 e / 2) D^2
+            float4* st = &stage[w][lane * 8];
+            st[0] = make_float4(float(xi), float(yi), float(t.x0 - xi), float(t.y0 - yi));
+            st[1] = make_float4(float(t.M[0]) * zs, float(t.M[1]) * zs, float(t.M[2]) * zs, float(t.M[3]) * zs);
+            st[2] = make_float4(float(t.a3x), float(t.a3y), float(geo.l2s), float(t.kappa * (0.5 * M_LOG2E)));
+            st[3] = make_float4(float(t.n0), float(t.nx), float(t.ny), float(G.sigma));
+            st[4] = make_float4(float(t.w0[0]), float(t.w0[1]), float(t.w0[2]), float(t.wx[0]));
+            st[5] = make_float4(float(t.wx[1]), float(t.wx[2]), float(t.wy[0]), float(t.wy[1]));
+            st[6] = make_float4(float(t.wy[2]), 0.f, 0.f, 0.f);
+            st[7] = make_float4(bbox[0], bbox[1], bbox[2], bbox[3]);
         }
-        int tx0, tx1, ty0, ty1;
-        float bbox[4];
-        cone_tiles(geo, V, tx0, tx1, ty0, ty1, bbox);
-        const int ncx = max(tx1 - tx0 + 1, 0), ncy = max(ty1 - ty0 + 1, 0);
-        TileGeo& t = geo.tg;
-        t.tx0 = tx0;
-        t.ty0 = ty0;
-        t.ncx = ncx;
-        t.count = ncx * ncy;
-        counts[slot] = uint32_t(ncx * ncy);
-        tgeo[slot] = t;
-        // Render record (field map in vrs_internal.h); the colour goes to
-        // the colour array (k_color).
-        const double xi = floor(t.x0), yi = floor(t.y0);
-        const float zs = float(sqrt(0.5 / M_LN2));  // |z|^2 = (log2 e / 2) D^2
-        float4* dst = reinterpret_cast<float4*>(proj + slot * kRec);
-        dst[0] = make_float4(float(xi), float(yi), float(t.x0 - xi), float(t.y0 - yi));
-        dst[1] = make_float4(float(t.M[0]) * zs, float(t.M[1]) * zs, float(t.M[2]) * zs, float(t.M[3]) * zs);
-        dst[2] = make_float4(float(t.a3x), float(t.a3y), float(geo.l2s), float(t.kappa * (0.5 * M_LOG2E)));
-        dst[3] = make_float4(float(t.n0), float(t.nx), float(t.ny), float(G.sigma));
-        dst[4] = make_float4(float(t.w0[0]), float(t.w0[1]), float(t.w0[2]), float(t.wx[0]));
-        dst[5] = make_float4(float(t.wx[1]), float(t.wx[2]), float(t.wy[0]), float(t.wy[1]));
-        dst[6].x = float(t.wy[2]);
-        dst[7] = make_float4(bbox[0], bbox[1], bbox[2], bbox[3]);
+        const uint64_t okm = __ballot(ok);
+        wave_sync_lds();
+        // Piece q = 64 c + lane of the wave's records: record q / 8, field q % 8.
+        float4* dst = reinterpret_cast<float4*>(proj + (size_t(v) * size_t(g.n) + size_t(wave_i0)) * kRec);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int q = c * 64 + lane;
+            if ((okm >> (q >> 3)) & 1ull) dst[q] = stage[w][q];
+        }
+        wave_sync_lds();
     }
 }
 
@@ -147,11 +170,6 @@ __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, floa
     }
 }
 
-__device__ inline void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // One wave per block owns 64 consecutive (view, Gaussian) slots and deals
 // their candidates out to its lanes 64 at a time, so every lane tests one
