@@ -198,3 +198,111 @@ def test_keys_sort_and_ranges_against_python():
             assert tuple(rg[t]) == (idx[0], idx[-1] + 1)
         else:
             assert tuple(rg[t]) == (0, 0)
+
+
+def _edge_argmin(cam, f, u, E, C, box):
+    """Brute force over the tile's four boundary edges in pixel space: the
+    pixel point with the smallest tangent-plane D^2 (dense sampling, then a
+    bounded scalar refinement on the best edge)."""
+    from scipy.optimize import minimize_scalar
+    x0, y0, x1, y1 = box
+    edges = [((x0, y0), (x1, y0)), ((x1, y0), (x1, y1)), ((x1, y1), (x0, y1)), ((x0, y1), (x0, y0))]
+    best = (np.inf, None)
+    for (ax, ay), (bx, by) in edges:
+        s = np.linspace(0.0, 1.0, 4001)
+        D = _pixel_D2(cam, f, u, E, C, ax + s * (bx - ax), ay + s * (by - ay))
+        k = int(np.argmin(D))
+        if not np.isfinite(D[k]):
+            continue
+        lo, hi = s[max(k - 1, 0)], s[min(k + 1, len(s) - 1)]
+        fun = lambda t: float(_pixel_D2(cam, f, u, E, C, np.array(ax + t * (bx - ax)), np.array(ay + t * (by - ay))))
+        r = minimize_scalar(fun, bounds=(lo, hi), method="bounded", options=dict(xatol=1e-13))
+        t, val = (r.x, r.fun) if r.fun <= D[k] else (s[k], D[k])
+        if val < best[0]:
+            best = (val, (ax + t * (bx - ax), ay + t * (by - ay)))
+    return best
+
+
+def _ray_argmax_depth(d, mu, Sig):
+    """1-D brute force: the ray parameter of maximum 3D Gaussian density along
+    the unit ray d (dense scan, then a bounded refinement)."""
+    from scipy.optimize import minimize_scalar
+    r = np.linalg.norm(mu)
+    # Far off the mean's direction the maximum can lie far along the ray, or
+    # behind the eye: scan a wide interval on the negative log-density.
+    ts = np.linspace(-200.0 * r, 200.0 * r, 400001)
+    Binv = np.linalg.inv(Sig)
+    x = ts[:, None] * d[None] - mu[None]
+    k = int(np.argmin(np.einsum("ki,ij,kj->k", x, Binv, x)))
+    nll = lambda t: float(0.5 * (t * d - mu) @ Binv @ (t * d - mu))
+    res = minimize_scalar(nll, bounds=(ts[max(k - 1, 0)], ts[min(k + 1, len(ts) - 1)]),
+                          method="bounded", options=dict(xatol=1e-13))
+    return res.x
+
+
+@pytest.mark.parametrize("fov,size,seed", [(100.0, 256, 300), (160.0, 128, 301)])
+def test_tile_depth_off_the_mean_is_depth_on_the_max_boundary_ray(fov, size, seed):
+    """Per-tile depth when the mean lies outside the tile (Sec. 4.2: the
+    depth is evaluated at the point of maximum density found by Eq. 4).
+
+    Independent of the tangent-plane back-projection: the pixel point of
+    maximum density on the tile boundary is found by brute force in image
+    space, and the depth is the 1-D argmax of the 3D density along that
+    point's unit ray.  The back-projected ray must also map back to qhat.
+    A sign or focal-length mistake in the back-projection fails both."""
+    from oracle import gaussian as g_mod
+    rng = np.random.default_rng(seed)
+    cam = synth.camera_translate((0, 0, 0), fov, size, size)
+    f = cam_mod.focal(cam)
+    grid = tiles_mod.TileGrid(size, size, 16)
+    checked, half_line, wrong_sign_caught, wrong_scale_caught = 0, 0, 0, 0
+    tanx = math.tan(math.radians(fov / 2))
+    for it in range(600):
+        if fov > 150 and it % 2:
+            # Large splats close to the eye, just outside the view: their
+            # far tiles cross the tangent plane's horizon (half-line edges).
+            z = rng.uniform(0.05, 0.4)
+            mu = np.array([rng.choice([-1, 1]) * rng.uniform(1.0, 3.0) * tanx * z,
+                           rng.uniform(-0.5, 0.5) * tanx * z, z])
+            Sig = g_mod.covariance(rng.standard_normal((4, 1)), rng.uniform(-1.5, 0.0, (3, 1)))[0]
+        else:
+            z = rng.uniform(0.5, 4)
+            mu = np.array([rng.uniform(-1.3, 1.3) * tanx * z, rng.uniform(-1.3, 1.3) * tanx * z, z])
+            Sig = g_mod.covariance(rng.standard_normal((4, 1)), rng.uniform(-3.5, -1.0, (3, 1)))[0]
+        op = proj_mod.optimal_projection(mu[None], Sig[None], f, 0.3)
+        x0 = cam.cx + f * mu[0] / mu[2]
+        y0 = cam.cy + f * mu[1] / mu[2]
+        tile = int(rng.integers(0, grid.n))
+        box = grid.boxes(np.array([tile]))
+        res = tiles_mod.quad_test(cam, f, op["u"], op["E"], op["conic"], np.array([x0]), np.array([y0]), *box)
+        D2 = res["D2min"][0]
+        if res["inside"][0] or not np.isfinite(D2) or D2 > 40.0:
+            continue
+        val, pt = _edge_argmin(cam, f, op["u"][0], op["E"][0], op["conic"][0], tuple(b[0] for b in box))
+        assert pt is not None and abs(val - D2) <= 1e-7 * max(1.0, D2)
+        half_line += int(not res["front"][0].all())
+        B = np.linalg.inv(Sig)
+        dep = tiles_mod.tile_depth(op["u"], op["E"], f, res["qhat"], mu[None], B[None])[0]
+        d_bf = cam_mod.ray_dirs(cam, pt[0], pt[1])
+        t_bf = _ray_argmax_depth(d_bf, mu, Sig)
+        rr = np.linalg.norm(mu)
+        assert abs(dep - t_bf) <= 1e-7 * rr, (dep, t_bf)
+        # Round trip: the back-projected ray has tangent coordinate qhat.
+        dd = op["u"][0] + op["E"][0] @ res["qhat"][0] / f
+        q_rt, h_rt = proj_mod.tangent_coords(dd / np.linalg.norm(dd), op["u"][0], op["E"][0], f)
+        assert h_rt > 0 and np.allclose(q_rt, res["qhat"][0], rtol=1e-10, atol=1e-9)
+        # The test has teeth: deliberately wrong back-projections disagree.
+        for wrong, counter in (((op["u"][0] - op["E"][0] @ res["qhat"][0] / f), "sign"),
+                               ((op["u"][0] + op["E"][0] @ res["qhat"][0]), "scale")):
+            w = wrong / np.linalg.norm(wrong)
+            tw = float((w @ B @ mu) / (w @ B @ w))
+            if abs(tw - t_bf) > 1e-5 * rr:
+                if counter == "sign":
+                    wrong_sign_caught += 1
+                else:
+                    wrong_scale_caught += 1
+        checked += 1
+    assert checked >= 40
+    assert wrong_sign_caught >= 0.8 * checked and wrong_scale_caught >= 0.8 * checked
+    if fov > 150:
+        assert half_line >= 3
