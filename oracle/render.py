@@ -50,6 +50,9 @@ class OracleOptions:
     record: bool = False
     eps_inst: float = 1e-9                # |ln alpha_hat - ln alpha_min| for instance flags
     shade: bool = True                    # False: stop after keys and ranges
+    alternatives: bool = False            # enumerate admissible outcomes of flagged samples
+    alt_cap: int = 256                    # most outcomes enumerated per sample or 2x2 group
+    alt_flips: int = 3                    # most decisions against FP64 on an enumerated path
 
 
 def preprocess_view(scene, cam, params):
@@ -164,6 +167,58 @@ def shade_samples(pre, cam, params, rays, entries_g, amb, opts):
                                   opts.flags, opts.record)
 
 
+def sample_alternatives(pre, cam, params, rays, entries_g, amb, samples, opts, chunk=16):
+    """Admissible outcomes of the given (flagged) samples: for each, a pair
+    (list of (rgba (4,), flips), complete) from ``blend.sample_outcomes`` over
+    the entries of its list that might reach alpha_min, following paths with
+    at most ``opts.alt_flips`` decisions against FP64 (fewer if that gives
+    more than ``opts.alt_cap`` outcomes), or None if even one such decision
+    gives too many."""
+    out = {}
+    g = np.asarray(entries_g, np.int64)
+    if len(samples) == 0:
+        return out
+    ln_amin = math.log(np.float64(params.alpha_min))
+    margin = opts.flags.eps_alpha * 1.5
+    bg = np.asarray(params.background, np.float64)
+    amb = np.asarray(amb, bool) if len(amb) else np.zeros(len(g), bool)
+    u, E, Cc = pre["u"][g], pre["E"][g], pre["C"][g]
+    lns = np.log(pre["sigma"][g])
+    for s0 in range(0, len(samples), chunk):
+        ss = np.asarray(samples[s0:s0 + chunk])
+        d = rays[ss]                                             # (S, 3)
+        h = d @ u.T                                              # (S, n)
+        q = pre["f"] * np.einsum("si,nik->snk", d, E) / h[..., None]
+        D2 = np.einsum("snk,nkl,snl->sn", q, Cc, q)
+        lnag = np.where(h > 0, lns[None] - 0.5 * D2, -np.inf)
+        for r, s in enumerate(ss):
+            cand = np.flatnonzero(lnag[r] >= ln_amin - margin)
+            gc = g[cand]
+            la = lnag[r, cand]
+            al = np.minimum(np.float64(params.alpha_max), np.exp(la))
+            Bd = np.einsum("i,nij->nj", d[r], pre["B"][gc])
+            ts = np.einsum("nj,nj->n", Bd, pre["mu_c"][gc]) / (Bd @ d[r])
+            # amb between candidates k and k+1 only if they are neighbours in the list.
+            ab = np.zeros(len(cand), bool)
+            if len(cand) > 1:
+                ab[:-1] = (cand[1:] == cand[:-1] + 1) & amb[cand[:-1]]
+            res = None
+            for mf in range(opts.alt_flips, 0, -1):
+                try:
+                    res = blend_mod.sample_outcomes(al, la, ts, pre["color"][gc], ab, int(params.window),
+                                                    np.float64(params.alpha_min), np.float64(params.t_min),
+                                                    opts.flags, opts.alt_cap, max_flips=mf)
+                    break
+                except blend_mod.TooManyOutcomes:
+                    continue
+            if res is None:
+                out[int(s)] = None
+                continue
+            leaves, complete = res
+            out[int(s)] = ([(np.r_[C + T * bg, 1.0 - T], flips) for C, T, flips in leaves], complete)
+    return out
+
+
 _WORK = {}
 
 
@@ -198,7 +253,93 @@ def _shade_job(job):
     bg = np.asarray(params.background, np.float64)
     rgb = C + T[:, None] * bg[None]
     rgba = np.concatenate([rgb, (1.0 - T)[:, None]], axis=1)
-    return (v, kind, tile, sub, (x0, y0, x1, y1), rgba, fl, stats, rec)
+    alts = None
+    if opts.alternatives and opts.flags is not None:
+        alts = sample_alternatives(pre, cam, params, rays, g_list, amb, np.flatnonzero(fl), opts)
+    return (v, kind, tile, sub, (x0, y0, x1, y1), rgba, fl, stats, rec, alts)
+
+
+def _place_alts(alts, unchecked, salts, pixels_of):
+    """Record the admissible outcomes of flagged samples at the pre-image
+    pixels each sample writes."""
+    for s, res in salts.items():
+        for yx in pixels_of(s):
+            if res is None:
+                unchecked[yx] = True
+            else:
+                leaves, complete = res
+                alts[yx] = (np.array([r for r, _ in leaves]), [f for _, f in leaves], complete)
+
+
+def _hybrid_alts(alts, unchecked, salts, base, wmask, x0, y0, x1, y1, cam, cap, max_flips):
+    """Admissible HYBRID pre-image values: the combinations of the admissible
+    outcomes of the samples of a 2x2 group (with at most ``max_flips``
+    decisions against FP64 over the group), mixed as the HYBRID rule mixes
+    them."""
+    wd = x1 - x0
+    groups = {}
+    for s in salts:
+        ly, lx = divmod(s, wd)
+        groups.setdefault((ly // 2 * 2, lx // 2 * 2), []).append(s)
+    for (gy, gx), _ in groups.items():
+        ys = range(gy, min(gy + 2, y1 - y0))
+        xs = range(gx, min(gx + 2, wd))
+        members = [(ly, lx) for ly in ys for lx in xs]
+        pix = [(y0 + ly, x0 + lx) for ly, lx in members]
+        opts_per = []
+        complete = True
+        bad = False
+        for ly, lx in members:
+            s = ly * wd + lx
+            if s in salts:
+                if salts[s] is None:
+                    bad = True
+                    break
+                leaves, comp = salts[s]
+                opts_per.append(leaves)
+                complete = complete and comp
+            else:
+                opts_per.append([(base[:, ly, lx], ())])
+        if bad:
+            for yx in pix:
+                unchecked[yx] = True
+            continue
+        combos = []
+
+        def walk(k, chosen, used):
+            nonlocal complete
+            if len(combos) > cap:
+                return
+            if k == len(opts_per):
+                combos.append(list(chosen))
+                return
+            for r, fl in opts_per[k]:
+                if used + len(fl) > max_flips:
+                    complete = False
+                    continue
+                chosen.append((r, fl))
+                walk(k + 1, chosen, used + len(fl))
+                chosen.pop()
+
+        walk(0, [], 0)
+        if len(combos) > cap:
+            for yx in pix:
+                unchecked[yx] = True
+            continue
+        vals = {yx: [] for yx in pix}
+        flips = {yx: [] for yx in pix}
+        w = wmask[y0 + gy:y0 + gy + len(ys), x0 + gx:x0 + gx + len(xs)]
+        for combo in combos:
+            grp = np.empty((4, len(ys), len(xs)))
+            for (ly, lx), (r, _) in zip(members, combo):
+                grp[:, ly - gy, lx - gx] = r
+            mixed = fov_mod.hybrid_mix(grp, w, x0 + gx, y0 + gy, cam.width, cam.height)
+            fl = tuple(f for _, fs in combo for f in fs)
+            for (ly, lx), yx in zip(members, pix):
+                vals[yx].append(mixed[:, ly - gy, lx - gx])
+                flips[yx].append(fl)
+        for yx in pix:
+            alts[yx] = (np.array(vals[yx]), flips[yx], complete)
 
 
 def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
@@ -305,6 +446,7 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
 
     # Step 5: assemble and compose.
     images, flagged, shaded = [], [], []
+    bits, alts, unchecked = [], [], []
     stats = dict(pairs=0, contrib=0, stopped=0, samples=0, jobs=len(jobs), t_keys=t_keys,
                  t_shade=t_shade)
     recs = {}
@@ -312,7 +454,10 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
         images.append(np.full((4, cam.height, cam.width), np.nan))
         flagged.append(np.zeros((cam.height, cam.width), bool))
         shaded.append(np.zeros((cam.height, cam.width), bool))
-    for (v, kind, tile, sub, box, rgba, fl, st, rec) in results:
+        bits.append(np.zeros((cam.height, cam.width), np.uint8))
+        alts.append({})
+        unchecked.append(np.zeros((cam.height, cam.width), bool))
+    for (v, kind, tile, sub, box, rgba, fl, st, rec, salts) in results:
         x0, y0, x1, y1 = box
         img, flg = images[v], flagged[v]
         for k in ("pairs", "contrib", "stopped"):
@@ -320,9 +465,14 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
         stats["samples"] += len(fl)
         if rec is not None:
             recs[(v, kind, tile, sub)] = rec
+        fb = fl.astype(np.uint8)
+        fl = fl != 0
         if kind == "plain":
             img[:, y0:y1, x0:x1] = rgba.T.reshape(4, y1 - y0, x1 - x0)
             flg[y0:y1, x0:x1] = fl.reshape(y1 - y0, x1 - x0)
+            bits[v][y0:y1, x0:x1] = fb.reshape(y1 - y0, x1 - x0)
+            if salts is not None:
+                _place_alts(alts[v], unchecked[v], salts, lambda s: [(y0 + s // (x1 - x0), x0 + s % (x1 - x0))])
         elif kind == "low":
             gw = (x1 - x0 + 1) // 2
             gh = (y1 - y0 + 1) // 2
@@ -330,22 +480,43 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
             fg = fl.reshape(gh, gw)
             up = np.repeat(np.repeat(vals, 2, axis=1), 2, axis=2)[:, :y1 - y0, :x1 - x0]
             fu = np.repeat(np.repeat(fg, 2, axis=0), 2, axis=1)[:y1 - y0, :x1 - x0]
+            bu = np.repeat(np.repeat(fb.reshape(gh, gw), 2, axis=0), 2, axis=1)[:y1 - y0, :x1 - x0]
             img[:, y0:y1, x0:x1] = up
             flg[y0:y1, x0:x1] = fu
+            bits[v][y0:y1, x0:x1] = bu
+            if salts is not None:
+                def pix(s, gw=gw, x0=x0, y0=y0, x1=x1, y1=y1):
+                    gy, gx = divmod(s, gw)
+                    return [(y, x) for y in range(y0 + 2 * gy, min(y0 + 2 * gy + 2, y1))
+                            for x in range(x0 + 2 * gx, min(x0 + 2 * gx + 2, x1))]
+                _place_alts(alts[v], unchecked[v], salts, pix)
         else:
             split, subc, wmask = classes[v]
-            vals = rgba.T.reshape(4, y1 - y0, x1 - x0)
+            base = rgba.T.reshape(4, y1 - y0, x1 - x0)
             f2 = fl.reshape(y1 - y0, x1 - x0)
-            if subc[y0 // 16, x0 // 16] == fov_mod.HYBRID:
-                vals = fov_mod.hybrid_mix(vals, wmask[y0:y1, x0:x1], x0, y0, cam.width, cam.height)
+            b2 = fb.reshape(y1 - y0, x1 - x0)
+            hybrid = subc[y0 // 16, x0 // 16] == fov_mod.HYBRID
+            vals = base
+            if hybrid:
+                vals = fov_mod.hybrid_mix(base, wmask[y0:y1, x0:x1], x0, y0, cam.width, cam.height)
                 # A flagged pixel taints its whole 2x2 group.
                 g = np.zeros_like(f2)
+                gb = np.zeros_like(b2)
                 for gy in range(0, f2.shape[0], 2):
                     for gx in range(0, f2.shape[1], 2):
                         g[gy:gy + 2, gx:gx + 2] = f2[gy:gy + 2, gx:gx + 2].any()
-                f2 = g
+                        gb[gy:gy + 2, gx:gx + 2] = np.bitwise_or.reduce(b2[gy:gy + 2, gx:gx + 2].ravel())
+                f2, b2 = g, gb
             img[:, y0:y1, x0:x1] = vals
             flg[y0:y1, x0:x1] = f2
+            bits[v][y0:y1, x0:x1] = b2
+            if salts is not None:
+                wd = x1 - x0
+                if not hybrid:
+                    _place_alts(alts[v], unchecked[v], salts, lambda s: [(y0 + s // wd, x0 + s % wd)])
+                else:
+                    _hybrid_alts(alts[v], unchecked[v], salts, base, wmask, x0, y0, x1, y1, cam, opts.alt_cap,
+                                 opts.alt_flips)
         shaded[v][y0:y1, x0:x1] = True
 
     finals, fflags, valid_px = [], [], []
@@ -386,6 +557,8 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
     stats["n_inst"] = int(len(skeys))
     stats["n_inst_border"] = int(all_border.sum())
     return dict(images=finals, pre_images=images, flags=fflags, valid=valid_px,
+                pre_flags=flagged, pre_flag_bits=bits, pre_alts=alts, pre_unchecked=unchecked,
+                shaded=shaded,
                 pre=pres, grids=grids, view_offsets=offs, n_tiles=off,
                 inst_tile=all_tile, inst_gid=all_gid, inst_depth=all_dep,
                 inst_border=all_border, keys=skeys, gids=sgids, depths=sdep,

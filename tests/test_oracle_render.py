@@ -269,3 +269,161 @@ def test_tiny_workload_flag_fraction_small():
     frac = res["flags"][0].mean()
     assert frac < 0.01, frac
     assert res["stats"]["n_inst"] > 10000
+
+
+# ---------------------------------------------------------------------------
+# Admissible outcomes of borderline samples (blend.sample_outcomes)
+# ---------------------------------------------------------------------------
+
+def _blend_in_order(alphas, colors, order, T_min=1e-4):
+    """Front-to-back compositing of the given entries in the given order,
+    written out directly: C = sum c_i a_i prod_{j<i}(1 - a_j), stopping before
+    the entry that would take T below T_min."""
+    T, C = 1.0, np.zeros(3)
+    for i in order:
+        Tn = T * (1.0 - alphas[i])
+        if Tn < T_min:
+            break
+        C = C + T * alphas[i] * np.asarray(colors[i], float)
+        T = Tn
+    return C, T
+
+
+def _outcome_set(leaves):
+    return sorted((tuple(np.round(C, 12)), round(T, 12)) for C, T, _ in leaves)
+
+
+def _expected_set(pairs):
+    return sorted((tuple(np.round(C, 12)), round(T, 12)) for C, T in pairs)
+
+
+def test_sample_outcomes_fp64_path_equals_window_blend():
+    """The outcome with no flipped decision is the window blend itself, on
+    random lists with overflowing windows."""
+    rng = np.random.default_rng(21)
+    flags = blend_mod.BlendFlags()
+    for W in (1, 3, 8):
+        for _ in range(20):
+            n = 50
+            al = rng.uniform(0.0, 0.6, n)
+            al[rng.random(n) < 0.3] = 0.001  # below alpha_min
+            ts = rng.uniform(1.0, 3.0, n)
+            col = rng.uniform(0, 1, (n, 3))
+            lnag = np.log(np.maximum(al, 1e-300))
+
+            def gen():
+                for i in range(n):
+                    yield (np.array([al[i]]), np.array([lnag[i]]), (lambda m, i=i: np.array([ts[i]])[m]),
+                           col[i], False)
+            C, T, fl, _, _ = blend_mod.window_blend(1, gen(), W, 1 / 255, 1e-4, flags)
+            keep = al >= 1 / 255
+            leaves, complete = blend_mod.sample_outcomes(al[keep], lnag[keep], ts[keep], col[keep],
+                                                         np.zeros(keep.sum(), bool), W, 1 / 255, 1e-4, flags)
+            assert complete
+            base = [(c, t) for c, t, f in leaves if not f]
+            assert len(base) == 1
+            np.testing.assert_allclose(base[0][0], C[0], atol=1e-15)
+            assert abs(base[0][1] - T[0]) <= 1e-15
+            assert (len(leaves) > 1) == bool(fl[0])
+
+
+def test_sample_outcomes_depth_near_tie_admits_both_orders():
+    """Two entries whose depths differ by 1e-7 relative meet at an emission
+    (W = 1): both blend orders are admitted, and nothing else."""
+    al = np.array([0.5, 0.3, 0.2])
+    col = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0]])
+    ts = np.array([2.0, 2.0 * (1 + 1e-7), 5.0])
+    leaves, _ = blend_mod.sample_outcomes(al, np.log(al), ts, col, np.zeros(3, bool), 1, 1 / 255, 1e-4,
+                                          blend_mod.BlendFlags())
+    want = [_blend_in_order(al, col, [0, 1, 2]), _blend_in_order(al, col, [1, 0, 2])]
+    assert _outcome_set(leaves) == _expected_set(want)
+    # Depths further apart than eps_t: one outcome.
+    ts2 = np.array([2.0, 2.0 * (1 + 1e-4), 5.0])
+    leaves, _ = blend_mod.sample_outcomes(al, np.log(al), ts2, col, np.zeros(3, bool), 1, 1 / 255, 1e-4,
+                                          blend_mod.BlendFlags())
+    assert _outcome_set(leaves) == _expected_set([_blend_in_order(al, col, [0, 1, 2])])
+
+
+def test_sample_outcomes_alpha_at_threshold_admits_skip_and_blend():
+    """An entry whose alpha is within eps_alpha of alpha_min may be skipped
+    or blended."""
+    amin = 1 / 255
+    al = np.array([0.4, amin * math.exp(1e-6), 0.25])
+    col = np.array([[0.2, 0.4, 0.6], [1.0, 1.0, 1.0], [0.9, 0.1, 0.3]])
+    ts = np.array([1.0, 1.5, 2.0])
+    leaves, _ = blend_mod.sample_outcomes(al, np.log(al), ts, col, np.zeros(3, bool), 4, amin, 1e-4,
+                                          blend_mod.BlendFlags())
+    want = [_blend_in_order(al, col, [0, 1, 2]), _blend_in_order(al, col, [0, 2])]
+    assert _outcome_set(leaves) == _expected_set(want)
+    kinds = {f[0][0] for _, _, f in leaves if f}
+    assert kinds == {blend_mod.FLAG_ALPHA}
+
+
+def test_sample_outcomes_transmittance_at_T_min_admits_stop_and_blend():
+    """An emission whose T' lands within eps_T of T_min may stop the sample
+    or blend the entry."""
+    T_min = 1e-4
+    a0 = 0.99
+    a1 = 1.0 - T_min * (1 + 1e-5) / (1.0 - a0)       # T' after entry 1 = T_min (1 + 1e-5)
+    al = np.array([a0, a1, 0.5])
+    col = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0]])
+    ts = np.array([1.0, 2.0, 3.0])
+    leaves, _ = blend_mod.sample_outcomes(al, np.log(al), ts, col, np.zeros(3, bool), 2, 1 / 255, T_min,
+                                          blend_mod.BlendFlags())
+    stop = _blend_in_order(al, col, [0])
+    # Blending entry 1 leaves T = T_min (1 + 1e-5); entry 2 then stops the sample.
+    go = _blend_in_order(al, col, [0, 1], T_min=0.0)
+    assert _outcome_set(leaves) == _expected_set([stop, go])
+
+
+def test_sample_outcomes_ambiguous_arrival_order():
+    """Two list neighbours with ambiguous key order: both arrival orders are
+    followed, which changes the window's content (W = 1): D(5), A(3), B(2)
+    blends A, B, D; swapped, D, B, A blends B, A, D."""
+    al = np.array([0.3, 0.4, 0.5])          # D, A, B
+    col = np.array([[0, 0, 1.0], [1.0, 0, 0], [0, 1.0, 0]])
+    ts = np.array([5.0, 3.0, 2.0])
+    amb = np.array([False, True, False])
+    leaves, _ = blend_mod.sample_outcomes(al, np.log(al), ts, col, amb, 1, 1 / 255, 1e-4,
+                                          blend_mod.BlendFlags())
+    want = [_blend_in_order(al, col, [1, 2, 0]), _blend_in_order(al, col, [2, 1, 0])]
+    assert _outcome_set(leaves) == _expected_set(want)
+
+
+def test_sample_outcomes_cap():
+    """Many simultaneous near-ties exceed the enumeration cap."""
+    n = 12
+    al = np.full(n, 0.05)
+    ts = 2.0 * (1 + 1e-8 * np.arange(n))
+    col = np.random.default_rng(3).uniform(0, 1, (n, 3))
+    with pytest.raises(blend_mod.TooManyOutcomes):
+        blend_mod.sample_outcomes(al, np.log(al), ts, col, np.zeros(n, bool), 2, 1 / 255, 1e-4,
+                                  blend_mod.BlendFlags(), cap=64)
+    # With a flip budget the enumeration stays small and says it is partial.
+    leaves, complete = blend_mod.sample_outcomes(al, np.log(al), ts, col, np.zeros(n, bool), 2, 1 / 255, 1e-4,
+                                                 blend_mod.BlendFlags(), cap=64, max_flips=1)
+    assert not complete and 1 < len(leaves) <= 64
+    assert sum(1 for _, _, f in leaves if not f) == 1 and all(len(f) <= 1 for _, _, f in leaves)
+
+
+def test_render_outcomes_cover_every_flagged_pixel():
+    """With outcome enumeration on, every flagged pre-compose pixel of a
+    foveated stereo render has admissible outcomes (or is counted as
+    unchecked), and the FP64 outcome among them is the oracle's own pixel,
+    HYBRID mixes included."""
+    scene, cams, fovs, params = synth.config_stereo(1, n=6000, width=160, height=128, radius_deg=14.0)
+    res = oracle.render(scene, cams, fovs, params, OracleOptions(alternatives=True))
+    n_alt = 0
+    for v in range(2):
+        fl = res["pre_flags"][v]
+        alts = res["pre_alts"][v]
+        unc = res["pre_unchecked"][v]
+        have = np.zeros_like(fl)
+        for (y, x), (vals, flips, _) in alts.items():
+            have[y, x] = True
+            base = [i for i, f in enumerate(flips) if not f]
+            assert base, (y, x)
+            np.testing.assert_allclose(vals[base[0]], res["pre_images"][v][:, y, x], atol=1e-12)
+            n_alt += len(vals) > 1
+        assert np.array_equal(fl, have | unc)
+    assert n_alt > 0
