@@ -43,6 +43,7 @@ typedef struct ihipStream_t* vrs_stream_t; /* hipStream_t */
 #define VRS_ERR_CAPACITY (-2)
 #define VRS_ERR_HIP (-3)
 #define VRS_ERR_UNSUPPORTED (-4)
+#define VRS_ERR_SCRATCH (-5) /* request larger than the fixed scratch of a no-allocation entry point */
 
 /* Limits. */
 #define VRS_MAX_VIEWS 32
@@ -210,6 +211,21 @@ int vrs_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t
                    int32_t key_bits, void* ws, size_t ws_bytes, int32_t* status_dev,
                    vrs_stream_t stream);
 size_t vrs_sort_pairs_workspace_size(size_t capacity);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as vrs_sort_pairs, same arguments and result, but its workspace is a
+ * fixed device array inside the library instead of caller memory, so the
+ * call allocates nothing.  Each GPU the library runs on holds its own array
+ * of vrs_sort_pairs_workspace_size(VRS_SORT_NOALLOC_MAX_PAIRS) bytes (about
+ * 33 MiB) until the process ends.  capacity > VRS_SORT_NOALLOC_MAX_PAIRS
+ * returns VRS_ERR_SCRATCH with nothing enqueued.  Every call on one GPU uses
+ * that GPU's one array: calls that may overlap on the same GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Nothing in the array needs to be cleared between calls. */
+#define VRS_SORT_NOALLOC_MAX_PAIRS 2097152u
+int vrs_sort_pairs_noalloc(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, size_t capacity,
+                           int32_t key_bits, int32_t* status_dev, vrs_stream_t stream);
 
 /* Tile ranges of sorted keys: ranges[t] = {first, last + 1} of global tile t,
  * {0, 0} for empty tiles.  ranges has tiles_total rows of two uint32. */

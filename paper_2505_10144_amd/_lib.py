@@ -13,6 +13,8 @@ VRS_ERR_INVALID_ARG = -1
 VRS_ERR_CAPACITY = -2
 VRS_ERR_HIP = -3
 VRS_ERR_UNSUPPORTED = -4
+VRS_ERR_SCRATCH = -5
+VRS_SORT_NOALLOC_MAX_PAIRS = 2097152
 VRS_MAX_VIEWS = 32
 VRS_MAX_WINDOW = 32
 VRS_RECORD_FLOATS = 32
@@ -83,6 +85,7 @@ SIGNATURES = {
                            _P, _P, _S, _P, _P]),
     "vrs_sort_pairs": (_I, [_P, _P, _P, _S, _I, _P, _S, _P, _P]),
     "vrs_sort_pairs_workspace_size": (_S, [_S]),
+    "vrs_sort_pairs_noalloc": (_I, [_P, _P, _P, _S, _I, _P, _P]),
     "vrs_tile_ranges": (_I, [_P, _P, _S, _U, _P, _P]),
     "vrs_sort": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
                       ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _S,

@@ -223,6 +223,7 @@ const char* vrs_status_string(int code) {
         case VRS_ERR_CAPACITY: return "VRS_ERR_CAPACITY";
         case VRS_ERR_HIP: return "VRS_ERR_HIP";
         case VRS_ERR_UNSUPPORTED: return "VRS_ERR_UNSUPPORTED";
+        case VRS_ERR_SCRATCH: return "VRS_ERR_SCRATCH";
         default: return "VRS_ERR_UNKNOWN";
     }
 }

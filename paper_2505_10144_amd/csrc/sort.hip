@@ -23,13 +23,8 @@
 
 namespace vrs {
 
-constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItemsPerLane = 8;
-constexpr int kSortTile = kSortThreads * kSortItemsPerLane;  // 2048 (twice the blocks of 4096-key tiles: better latency hiding, 3 % faster sort)
-constexpr int kRadix = 256;
 constexpr uint64_t kDeadKey = ~0ull;
-constexpr int kMaxPasses = 8;
 static_assert(kSortThreads == kRadix, "one thread per digit in the count kernels");
 
 // ---------------------------------------------------------------------------
@@ -379,17 +374,7 @@ __global__ void k_tile_ranges(const uint64_t* __restrict__ keys, const uint32_t*
 // ---------------------------------------------------------------------------
 static size_t sort_blocks(size_t capacity) { return (capacity + kSortTile - 1) / kSortTile; }
 
-// Workspace: ping-pong pairs, the [256][blocks] histogram of one pass, the
-// digit offsets of every pass, and the per-tile digit counts of every pass.
-size_t sort_ws_bytes(size_t capacity) {
-    const size_t nb = sort_blocks(capacity) ? sort_blocks(capacity) : 1;
-    size_t b = capacity * (sizeof(uint64_t) + sizeof(uint32_t));  // ping-pong buffers
-    b = (b + 255) & ~size_t(255);
-    b += ((size_t(kRadix) * nb + 63) & ~size_t(63)) * sizeof(uint32_t);
-    b += size_t(kMaxPasses) * kRadix * sizeof(uint32_t);
-    b += size_t(kMaxPasses) * nb * kRadix * sizeof(uint32_t);
-    return b;
-}
+size_t sort_ws_bytes(size_t capacity) { return sort_ws_layout_bytes(capacity); }
 
 int launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return VRS_OK;

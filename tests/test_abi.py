@@ -122,3 +122,17 @@ def test_entry_points_validate_before_device_work():
     assert lib.vrs_render_foveated(null, -1, null, null, cam, fov, 1, ctypes.byref(p), null, 0, imgs, null, 0,
                                    null, null) == L.VRS_ERR_INVALID_ARG
     assert L.load().vrs_sort_pairs_workspace_size(0) > 0
+
+
+def test_noalloc_sort_rejects_requests_beyond_its_scratch():
+    """The no-allocation sort refuses capacities beyond its fixed scratch
+    array on the host, before any device call, and checks its arguments."""
+    lib = L.load()
+    big = L.VRS_SORT_NOALLOC_MAX_PAIRS + 1
+    assert lib.vrs_sort_pairs_noalloc(None, None, ctypes.c_void_p(16), big, 40, None, None) == L.VRS_ERR_SCRATCH
+    assert L.status_string(L.VRS_ERR_SCRATCH) == "VRS_ERR_SCRATCH"
+    assert lib.vrs_sort_pairs_noalloc(None, None, None, 10, 40, None, None) == L.VRS_ERR_INVALID_ARG
+    assert lib.vrs_sort_pairs_noalloc(None, None, ctypes.c_void_p(16), 10, 65, None, None) == L.VRS_ERR_INVALID_ARG
+    assert lib.vrs_sort_pairs_noalloc(None, None, ctypes.c_void_p(16), 10, 40, None, None) == L.VRS_ERR_INVALID_ARG
+    # The scratch holds the workspace of the largest request.
+    assert lib.vrs_sort_pairs_workspace_size(L.VRS_SORT_NOALLOC_MAX_PAIRS) < 40 << 20
