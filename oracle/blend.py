@@ -12,7 +12,8 @@ by the per-tile key; level 2 is a per-sample window of W entries.  For each
 list entry in order (arrival index a) whose alpha at the sample reaches
 alpha_min, (t*, a, alpha, colour) is inserted; whenever the window holds more
 than W entries, the one with the smallest (t*, a) is blended.  At the end of
-the list the rest is blended in ascending (t*, a) order.
+the list the rest is blended in ascending (t*, a) order.  W = 0 blends every
+entry on arrival, in list order: the renderers that only sort globally.
 
 Blending one entry (3DGS conventions, a reading): alpha is clamped to
 alpha_max = 0.99; T' = T (1 - alpha); if T' < T_min = 1e-4 the sample stops and
@@ -39,7 +40,7 @@ class BlendFlags:
     """Relative distances to the discrete decisions below which a sample is
     flagged as borderline (FP32 vs FP64 may decide differently there)."""
 
-    def __init__(self, eps_alpha=1e-5, eps_t=1e-5, eps_T=1e-3):
+    def __init__(self, eps_alpha=1e-5, eps_t=2e-6, eps_T=1e-3):
         self.eps_alpha = eps_alpha  # |ln(sigma G) - ln(alpha_min)|
         self.eps_t = eps_t          # |t1 - t2| / max(|t1|, |t2|) at an emission
         self.eps_T = eps_T          # |T' - T_min| / T_min at an emission

@@ -35,6 +35,8 @@ LOW, HIGH, HYBRID = 0, 1, 2
 
 def mask_weights(cam, fovea, px, py):
     """w(p) at continuous pixel positions."""
+    if getattr(fovea, "shape", 0) == 1:
+        return rect_weights(fovea, px, py)
     d = cam_mod.ray_dirs(cam, px, py)
     dc = cam_mod.ray_dirs(cam, np.float64(fovea.center_px[0]), np.float64(fovea.center_px[1]))
     cosang = np.clip(d @ dc, -1.0, 1.0)
@@ -46,6 +48,28 @@ def mask_weights(cam, fovea, px, py):
     if b <= 0:
         return (e <= rho).astype(np.float64)
     return np.clip((rho * (1.0 + b) - e) / (rho * b), 0.0, 1.0)
+
+
+def rect_weights(fovea, px, py):
+    """The paper's layout (Sec. 5): a centre rectangle with half-extents
+    (hx, hy) around center_px and a band of band_frac of it in which the
+    weights rise linearly.  Reading: per axis
+    u = clamp((h (1 + b) - |p - c|) / (h b), 0, 1), and w = min(u_x, u_y)
+    (w = 1 on the rectangle, 0 outside the padded one); without a band, w is
+    1 on the closed rectangle and 0 elsewhere."""
+    b = np.float64(fovea.band_frac)
+    out = None
+    for p, c, h in ((px, fovea.center_px[0], fovea.half_px[0]), (py, fovea.center_px[1], fovea.half_px[1])):
+        dist = np.abs(np.asarray(p, np.float64) - np.float64(c))
+        h = np.float64(h)
+        if h <= 0:
+            u = np.zeros_like(dist)
+        elif b <= 0:
+            u = (dist <= h).astype(np.float64)
+        else:
+            u = np.clip((h * (1.0 + b) - dist) / (h * b), 0.0, 1.0)
+        out = u if out is None else np.minimum(out, u)
+    return out
 
 
 def classify(cam, fovea):

@@ -254,3 +254,208 @@ def loss_numpy(scene, cams, params, targets):
     l1 = sum(np.abs(i[:3] - t[:3]).sum() for i, t in zip(imgs, targets))
     l2 = sum(((i[:3] - t[:3]) ** 2).sum() for i, t in zip(imgs, targets))
     return l1 / n + 0.2 * l2 / n, res
+
+
+# ---------------------------------------------------------------------------
+# Foveated views: gradients through the HYBRID mix and the periphery's
+# nearest-neighbour upsampling and blur (Sec. 4.3).
+# ---------------------------------------------------------------------------
+
+def _sample_positions(kind, box, cam):
+    """Continuous image positions of a render job's samples, in the order the
+    forward pass records them: pixel centres, or for a LOW tile the centres
+    (2i + 1, 2j + 1) of its aligned 2x2 groups."""
+    x0, y0, x1, y1 = box
+    if kind == "low":
+        GX, GY = np.meshgrid(np.arange(x0, x1, 2), np.arange(y0, y1, 2))
+        return GX.ravel() + 1.0, GY.ravel() + 1.0
+    return cam_mod.pixel_centers(x0, y0, x1, y1)
+
+
+def fov_sample_lists(res, cams):
+    """Per view: sample positions (px, py), the emitted Gaussian ids of every
+    sample (S, K, -1 padded), and the two linear maps of the foveated
+    composition as COO triplets: A (pre-compose pixel <- sample: identity for
+    plain and HIGH pixels, w c_p + (1 - w)/n sum of the 2x2 group for HYBRID
+    pixels, the group value for the pixels of a LOW group) and B (final pixel
+    <- pre-compose pixel: the 3x3 binomial blur, edge-clamped, for LOW
+    pixels, identity otherwise)."""
+    from . import fovea as fov_mod
+    out = []
+    for v, cam in enumerate(cams):
+        W, H = cam.width, cam.height
+        grid = res["grids"][v]
+        off = res["view_offsets"][v]
+        cls = res["classes"][v]
+        pxs, pys, seqs = [], [], []
+        ar, ac, av = [], [], []
+        for (vv, kind, tile, sub), rec in res["records"].items():
+            if vv != v:
+                continue
+            s, e = res["ranges"][off + tile]
+            lst = res["gids"][s:e]
+            if kind == "sub":
+                tx, ty = tile % grid.ntx, tile // grid.ntx
+                bx0, by0 = tx * 32 + (sub % 2) * 16, ty * 32 + (sub // 2) * 16
+                box = (bx0, by0, min(bx0 + 16, W), min(by0 + 16, H))
+            else:
+                box = grid.box(tile)
+            px, py = _sample_positions(kind, box, cam)
+            base = len(seqs)
+            for k, seq in enumerate(rec):
+                pxs.append(px[k]); pys.append(py[k])
+                seqs.append([int(lst[a]) for a, _ in seq])
+            x0, y0, x1, y1 = box
+            if kind == "plain":
+                for k in range(len(rec)):
+                    ly, lx = divmod(k, x1 - x0)
+                    ar.append((y0 + ly) * W + (x0 + lx)); ac.append(base + k); av.append(1.0)
+                continue
+            if kind == "low":
+                gw = (x1 - x0 + 1) // 2
+                for k in range(len(rec)):
+                    gy, gx = divmod(k, gw)
+                    for yy in range(y0 + 2 * gy, min(y0 + 2 * gy + 2, y1)):
+                        for xx in range(x0 + 2 * gx, min(x0 + 2 * gx + 2, x1)):
+                            ar.append(yy * W + xx); ac.append(base + k); av.append(1.0)
+                continue
+            wd = x1 - x0
+            hybrid = kind == "sub" and cls[1][y0 // 16, x0 // 16] == fov_mod.HYBRID
+            for k in range(len(rec)):
+                ly, lx = divmod(k, wd)
+                p = (y0 + ly) * W + (x0 + lx)
+                if not hybrid:
+                    ar.append(p); ac.append(base + k); av.append(1.0)
+                    continue
+                w = float(cls[2][y0 + ly, x0 + lx])
+                gy0, gx0 = ly // 2 * 2, lx // 2 * 2
+                members = [(yy, xx) for yy in range(gy0, min(gy0 + 2, y1 - y0))
+                           for xx in range(gx0, min(gx0 + 2, wd))]
+                ar.append(p); ac.append(base + k); av.append(w)
+                for yy, xx in members:
+                    ar.append(p); ac.append(base + yy * wd + xx); av.append((1.0 - w) / len(members))
+        K = max([len(sq) for sq in seqs] + [1])
+        E = np.full((len(seqs), K), -1, np.int64)
+        for i, sq in enumerate(seqs):
+            E[i, :len(sq)] = sq
+        # B: blur of LOW pixels (none in a plain view).
+        if cls is None:
+            low = np.zeros((H, W), bool)
+        else:
+            low = np.repeat(np.repeat(cls[1] == fov_mod.LOW, 16, 0), 16, 1)[:H, :W]
+        br, bc, bv = [], [], []
+        ys, xs = np.nonzero(~low)
+        br += list(ys * W + xs); bc += list(ys * W + xs); bv += [1.0] * len(ys)
+        ys, xs = np.nonzero(low)
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                ny = np.clip(ys + dy, 0, H - 1)
+                nx = np.clip(xs + dx, 0, W - 1)
+                br += list(ys * W + xs); bc += list(ny * W + nx)
+                bv += [float(fov_mod.BLUR[dy + 1, dx + 1])] * len(ys)
+        out.append(dict(px=np.asarray(pxs), py=np.asarray(pys), E=E,
+                        A=(np.asarray(ar, np.int64), np.asarray(ac, np.int64), np.asarray(av)),
+                        B=(np.asarray(br, np.int64), np.asarray(bc, np.int64), np.asarray(bv))))
+    return out
+
+
+def _replay_samples(tensors, sh_degree, cam, params, px, py, E):
+    """Differentiable RGBA (S, 4) of samples at continuous positions (px, py)
+    blending their recorded Gaussians E (S, K) in order: the arithmetic of
+    ``replay`` at arbitrary sample positions."""
+    means, log_scales, quats, logits, sh = tensors
+    R = quat_to_rotmat_torch(quats)
+    s = torch.exp(log_scales).T
+    RS = R * s[:, None, :]
+    Sigma = RS @ RS.transpose(1, 2)
+    sigma = 1.0 / (1.0 + torch.exp(-logits))
+    K = (sh_degree + 1) ** 2
+    Rv_np, tv_np = cam_mod.rt(cam)
+    Rv = torch.tensor(Rv_np, dtype=DT)
+    tv = torch.tensor(tv_np, dtype=DT)
+    f = float(cam_mod.focal(cam))
+    mu_c = means.T @ Rv.T + tv
+    Sigma_c = Rv @ Sigma @ Rv.T
+    r = torch.linalg.norm(mu_c, dim=1)
+    u = mu_c / r[:, None]
+    ux, uy, uz = u[:, 0], u[:, 1], u[:, 2]
+    kk = 1.0 / (1.0 + uz)
+    e1 = torch.stack([1 - ux * ux * kk, -ux * uy * kk, -ux], dim=1)
+    e2 = torch.stack([-ux * uy * kk, 1 - uy * uy * kk, -uy], dim=1)
+    Emat = torch.stack([e1, e2], dim=2)
+    S2 = (f * f / (r * r))[:, None, None] * (Emat.transpose(1, 2) @ Sigma_c @ Emat)
+    S2 = S2 + float(params.dilation) * torch.eye(2, dtype=DT)[None]
+    C = torch.linalg.inv(S2)
+    o = torch.tensor(cam_mod.eye_center(cam), dtype=DT)
+    vd = means.T - o
+    vd = vd / torch.linalg.norm(vd, dim=1, keepdim=True)
+    Y = sh_basis_torch(sh_degree, vd)
+    col = torch.clamp_min(torch.einsum("nk,kcn->nc", Y, sh[:K]) + 0.5, 0.0)
+    bg = torch.tensor(params.background, dtype=DT)
+    S = len(px)
+    if S == 0:
+        return torch.zeros(0, 4, dtype=DT)
+    pxt = torch.tensor(px, dtype=DT)
+    pyt = torch.tensor(py, dtype=DT)
+    d = torch.stack([(pxt - float(cam.cx)) / f, (pyt - float(cam.cy)) / f, torch.ones_like(pxt)], dim=1)
+    d = d / torch.linalg.norm(d, dim=1, keepdim=True)
+    Et = torch.tensor(E, dtype=torch.long)
+    valid = Et >= 0
+    g = Et.clamp_min(0)
+    dd = d[:, None, :].expand(-1, g.shape[1], -1)
+    h = (dd * u[g]).sum(-1)
+    q = f * torch.einsum("pki,pkij->pkj", dd, Emat[g]) / h[..., None]
+    D2 = torch.einsum("pki,pkij,pkj->pk", q, C[g], q)
+    a = torch.minimum(torch.tensor(float(params.alpha_max), dtype=DT), sigma[g] * torch.exp(-0.5 * D2))
+    a = torch.where(valid, a, torch.zeros_like(a))
+    one_m = 1.0 - a
+    T_excl = torch.cumprod(torch.cat([torch.ones(S, 1, dtype=DT), one_m[:, :-1]], dim=1), dim=1)
+    Tfin = torch.prod(one_m, dim=1)
+    rgb = ((a * T_excl)[..., None] * col[g]).sum(1) + Tfin[:, None] * bg[None]
+    return torch.cat([rgb, (1.0 - Tfin)[:, None]], dim=1)
+
+
+def _apply(coo, x, n_out):
+    """y = M x for M given as COO triplets (rows, cols, vals); x (n_in, C)."""
+    rows, cols, vals = coo
+    y = torch.zeros(n_out, x.shape[1], dtype=DT)
+    return y.index_add(0, torch.tensor(rows), x[torch.tensor(cols)] * torch.tensor(vals, dtype=DT)[:, None])
+
+
+def replay_foveated(tensors, sh_degree, cams, params, lists):
+    """Differentiable final images (4, H, W) of foveated views from the raw
+    parameters: recorded per-sample blends, then the HYBRID mix / LOW
+    upsampling (A) and the periphery blur (B)."""
+    imgs = []
+    for cam, L in zip(cams, lists):
+        s = _replay_samples(tensors, sh_degree, cam, params, L["px"], L["py"], L["E"])
+        n = cam.width * cam.height
+        pre = _apply(L["A"], s, n)
+        fin = _apply(L["B"], pre, n)
+        imgs.append(fin.T.reshape(4, cam.height, cam.width))
+    return imgs
+
+
+def vjp_foveated(scene, cams, foveas, params, grad_images, workers=1, mask_flagged=False, masks=None):
+    """Vector-Jacobian product of the foveated renderer: the gradient of
+    sum_v <grad_images[v], I_v> (final images, all four channels) with
+    respect to the raw parameters, for the discrete state of the NumPy
+    forward pass.  With ``mask_flagged`` grad_images is taken as zero at
+    pixels the forward pass flags as borderline.  Returns (grads, forward
+    result, the grad_images used)."""
+    opts = OracleOptions(record=True, workers=workers)
+    res = render_full(scene, cams, foveas, params, opts, masks=masks)
+    used = []
+    for v, gi in enumerate(grad_images):
+        gi = np.array(gi, np.float64, copy=True)
+        if mask_flagged:
+            gi[:, res["flags"][v]] = 0.0
+        used.append(gi)
+    lists = fov_sample_lists(res, cams)
+    ts = [torch.tensor(np.asarray(a, np.float64), dtype=DT, requires_grad=True)
+          for a in (scene.means, scene.log_scales, scene.quats, scene.opacity_logits, scene.sh)]
+    imgs = replay_foveated(ts, scene.sh_degree, cams, params, lists)
+    total = sum((torch.tensor(gi, dtype=DT) * im).sum() for gi, im in zip(used, imgs))
+    total.backward()
+    names = ("means", "log_scales", "quats", "opacity_logits", "sh")
+    return {n: t.grad.numpy().copy() for n, t in zip(names, ts)}, res, used, [i.detach().numpy() for i in imgs]

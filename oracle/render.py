@@ -88,7 +88,7 @@ def preprocess_view(scene, cam, params):
                 lam_max=lam_max, f=f, near_gap=mu_c[:, 2] - np.float64(params.z_near))
 
 
-def _candidates(pre, cam, grid, opts, tile_subset=None):
+def _candidates(pre, cam, grid, opts, tile_subset=None, visible=None):
     gid = np.flatnonzero(pre["valid"])
     if opts.exhaustive_tiles:
         tiles = np.arange(grid.n)
@@ -110,12 +110,20 @@ def _candidates(pre, cam, grid, opts, tile_subset=None):
     if tile_subset is not None:
         keep = np.isin(Tt, tile_subset)
         G, Tt = G[keep], Tt[keep]
+    if visible is not None:
+        keep = visible[Tt]
+        G, Tt = G[keep], Tt[keep]
     return G, Tt
 
 
-def instances_view(pre, cam, grid, params, opts, tile_subset=None, chunk=400_000):
-    """Step 2 for one view: kept (tile, gid, depth) plus borderline flags."""
-    G, Tt = _candidates(pre, cam, grid, opts, tile_subset)
+def instances_view(pre, cam, grid, params, opts, tile_subset=None, chunk=400_000, visible=None):
+    """Step 2 for one view: kept (tile, gid, depth) plus borderline flags.
+    ``visible`` (bool per tile, or None) restricts instances to visible tiles
+    (visibility culling, Sec. 4.3).  The key depth is the per-tile depth at
+    the maximum point (params.depth 0, Sec. 4.2), or one depth per Gaussian:
+    view-space z (1) or the distance from the eye (2), the orders of the
+    Mini-Splatting (z) and (Dist) comparison renderers (Sec. 5)."""
+    G, Tt = _candidates(pre, cam, grid, opts, tile_subset, visible)
     out_t, out_g, out_d, out_b, out_D2 = [], [], [], [], []
     f = pre["f"]
     ln_amin = math.log(np.float64(params.alpha_min))
@@ -129,7 +137,13 @@ def instances_view(pre, cam, grid, params, opts, tile_subset=None, chunk=400_000
         lnah = np.log(pre["sigma"][g]) - 0.5 * D2
         keep = lnah >= ln_amin
         border = np.abs(lnah - ln_amin) < opts.eps_inst
-        dep = tiles_mod.tile_depth(pre["u"][g], pre["E"][g], f, res["qhat"], pre["mu_c"][g], pre["B"][g])
+        mode = int(getattr(params, "depth", 0))
+        if mode == 0:
+            dep = tiles_mod.tile_depth(pre["u"][g], pre["E"][g], f, res["qhat"], pre["mu_c"][g], pre["B"][g])
+        elif mode == 1:
+            dep = pre["mu_c"][g, 2]          # view-space z of the mean
+        else:
+            dep = pre["r"][g]                # distance from the eye to the mean
         out_t.append(t[keep]); out_g.append(g[keep]); out_d.append(dep[keep])
         out_b.append(border[keep]); out_D2.append(D2[keep])
     cat = (lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(0, dt))
@@ -342,16 +356,21 @@ def _hybrid_alts(alts, unchecked, salts, base, wmask, x0, y0, x1, y1, cam, cap, 
             alts[yx] = (np.array(vals[yx]), flips[yx], complete)
 
 
-def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
+def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None, masks=None):
     """Full forward pass.  ``foveas`` is one Fovea per view (or a single Fovea
     for all views); foveated views use 32x32 sort tiles, plain views use
-    ``params.tile``.  Returns a dict with per-view images (4, H, W) (NaN where
-    not shaded in sampled mode), per-pixel flags, instance data, sorted
-    keys/gids, ranges and counters."""
+    ``params.tile``.  ``masks`` optionally gives per view a visibility mask
+    (uint8 [H][W], nonzero = visible, or None): instances in tiles without a
+    visible pixel are culled (Sec. 4.3).  Returns a dict with per-view images
+    (4, H, W) (NaN where not shaded in sampled mode), per-pixel flags,
+    instance data, sorted keys/gids, ranges and counters."""
+    from . import visibility as vis_mod
     opts = opts or OracleOptions()
     if not isinstance(foveas, (list, tuple)):
         foveas = [foveas] * len(cams)
     V = len(cams)
+    masks = list(masks) if masks is not None else [None] * V
+    vis_bits = []
     t_start = time.perf_counter()
     pres, grids, insts, offs = [], [], [], []
     off = 0
@@ -372,7 +391,10 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
                         nb.append(((ty + dy) * grid.ntx + tx + dx)[ok])
                 want = np.unique(np.concatenate(nb))
             subset = want
-        inst = instances_view(pre, cam, grid, params, opts, subset)
+        vbits = vis_mod.tile_bits(masks[v], T) if masks[v] is not None else None
+        vis_bits.append(vbits)
+        inst = instances_view(pre, cam, grid, params, opts, subset,
+                              visible=vbits.ravel() if vbits is not None else None)
         pres.append(pre); grids.append(grid); insts.append((inst, subset))
         offs.append(off)
         off += grid.n
@@ -404,7 +426,7 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
 
     t_keys = time.perf_counter() - t_start
     if not opts.shade:
-        return dict(pre=pres, grids=grids, view_offsets=offs, n_tiles=off, inst_tile=all_tile,
+        return dict(pre=pres, grids=grids, view_offsets=offs, n_tiles=off, inst_tile=all_tile, vis_bits=vis_bits,
                     inst_gid=all_gid, inst_depth=all_dep, inst_border=all_border, keys=skeys,
                     gids=sgids, depths=sdep, ranges=ranges,
                     stats=dict(n_inst=int(len(skeys)), t_keys=t_keys))
@@ -557,7 +579,7 @@ def render(scene, cams, foveas, params, opts: Optional[OracleOptions] = None):
     stats["n_inst"] = int(len(skeys))
     stats["n_inst_border"] = int(all_border.sum())
     return dict(images=finals, pre_images=images, flags=fflags, valid=valid_px,
-                pre_flags=flagged, pre_flag_bits=bits, pre_alts=alts, pre_unchecked=unchecked,
+                pre_flags=flagged, pre_flag_bits=bits, pre_alts=alts, pre_unchecked=unchecked, vis_bits=vis_bits,
                 shaded=shaded,
                 pre=pres, grids=grids, view_offsets=offs, n_tiles=off,
                 inst_tile=all_tile, inst_gid=all_gid, inst_depth=all_dep,

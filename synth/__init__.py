@@ -14,7 +14,7 @@ from .scenes import (  # noqa: F401
     Params, Camera, Fovea, Scene,
     default_params, make_scene, uniform_scene, cluster_scene,
     camera_lookat, camera_translate, stereo_head, ring_cameras,
-    fovea_off, fovea_at_center,
+    fovea_off, fovea_at_center, fovea_rect, lens_mask, LENS_AXES,
     config_tiny, config_stereo, config_unpruned, config_batch, config_diff,
     subset_scene, permute_scene,
 )

@@ -37,9 +37,13 @@ class Params:
     ``blend_batch`` is the number of list entries staged per wave and batch
     and ``schedule`` selects the blend launch (0 one block per work item,
     1 persistent waves); both are performance knobs that never change the
-    output."""
+    output.  ``depth`` is the key depth of the sort: 0 the per-tile depth at
+    the splat's maximum point (the method), 1 view-space z, 2 distance to the
+    eye (the global-sort orders of the comparison systems); ``window`` 0
+    blends in key order without per-sample resorting."""
     tile: int = 16
     window: int = 16
+    depth: int = 0
     blend_batch: int = 64
     schedule: int = 0
     z_near: float = float(F32(0.2))
@@ -73,10 +77,16 @@ class Camera:
 
 @dataclasses.dataclass
 class Fovea:
+    """Full-resolution centre region.  shape 0: a disc of radius_deg (angle
+    around the ray through center_px); shape 1: a rectangle of half-extents
+    half_px (pixels) around center_px.  band_frac: the blending band's width
+    as a fraction of the radius or half-extent."""
     enabled: bool
     center_px: Tuple[float, float] = (0.0, 0.0)
     radius_deg: float = 15.0
     band_frac: float = 0.10
+    shape: int = 0
+    half_px: Tuple[float, float] = (0.0, 0.0)
 
 
 @dataclasses.dataclass
@@ -167,6 +177,33 @@ def fovea_at_center(cam: Camera, radius_deg=15.0, band_frac=0.10) -> Fovea:
     return Fovea(enabled=True, center_px=(cam.cx, cam.cy),
                  radius_deg=float(F32(radius_deg)),
                  band_frac=float(F32(band_frac)))
+
+
+def fovea_rect(cam: Camera, frac=0.5, band_frac=0.10) -> Fovea:
+    """The paper's layout (Sec. 5): a centre region of ``frac`` of the image
+    size in each dimension around the principal point, with a band of
+    band_frac of it."""
+    return Fovea(enabled=True, center_px=(cam.cx, cam.cy), radius_deg=0.0,
+                 band_frac=float(F32(band_frac)), shape=1,
+                 half_px=(float(F32(frac * cam.width / 2.0)), float(F32(frac * cam.height / 2.0))))
+
+
+# Semi-axes of the synthetic lens mask as fractions of the half image size:
+# chosen so that 508 of the 4615 32x32 tiles of a 2064x2272 eye are
+# invisible, next to the 507 the paper reports for its headset (Sec. 5.4;
+# the symmetric ellipse moves the count in steps of four).
+LENS_AXES = (1.087, 1.087)
+
+
+def lens_mask(width: int, height: int, axes=LENS_AXES) -> np.ndarray:
+    """Synthetic head-mounted-display visibility mask (uint8 [height][width],
+    1 = visible): the pixels whose centres lie inside an ellipse around the
+    image centre with semi-axes axes * (width/2, height/2).  A stand-in for
+    the mask a headset runtime provides."""
+    ys, xs = np.mgrid[0:height, 0:width]
+    u = (xs + 0.5 - width / 2.0) / (axes[0] * width / 2.0)
+    v = (ys + 0.5 - height / 2.0) / (axes[1] * height / 2.0)
+    return (u * u + v * v <= 1.0).astype(np.uint8)
 
 
 def _random_quats(rng, n):

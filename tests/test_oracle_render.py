@@ -427,3 +427,48 @@ def test_render_outcomes_cover_every_flagged_pixel():
             n_alt += len(vals) > 1
         assert np.array_equal(fl, have | unc)
     assert n_alt > 0
+
+
+# ---------------------------------------------------------------------------
+# Global-sort variants: view-z / distance keys, no per-sample resort (W = 0)
+# ---------------------------------------------------------------------------
+
+def test_window_zero_blends_in_list_order():
+    rng = np.random.default_rng(31)
+    n = 40
+    al = rng.uniform(0.0, 0.5, n)
+    ts = rng.uniform(1, 3, n)
+    col = rng.uniform(0, 1, (n, 3))
+
+    def gen():
+        for i in range(n):
+            yield (np.array([al[i]]), np.array([np.log(max(al[i], 1e-300))]),
+                   (lambda m, i=i: np.array([ts[i]])[m]), col[i], False)
+    C, T, *_ = blend_mod.window_blend(1, gen(), 0, 1 / 255, 1e-4)
+    keep = [i for i in range(n) if al[i] >= 1 / 255]
+    Cw, Tw = _blend_in_order(al, col, keep)
+    np.testing.assert_allclose(C[0], Cw, atol=1e-15)
+    assert abs(T[0] - Tw) <= 1e-15
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_global_sort_keys_with_no_resort_equal_per_pixel_key_order(depth):
+    """With one key depth per Gaussian (view z or distance) and W = 0, every
+    pixel composites all Gaussians reaching alpha_min in order of that depth
+    (ties by index): written out per pixel over all Gaussians, no tiles."""
+    scene, cam, params = _small(seed=5, n=200, size=40, window=0)
+    params = params.replace(depth=depth)
+    res = oracle.render(scene, [cam], synth.fovea_off(), params)
+    pre = preprocess_view(scene, cam, params)
+    gids = np.flatnonzero(pre["valid"])
+    key = pre["mu_c"][:, 2] if depth == 1 else pre["r"]
+    rng = np.random.default_rng(3)
+    for x, y in zip(rng.integers(0, 40, 40), rng.integers(0, 40, 40)):
+        d = cam_mod.ray_dirs(cam, x + 0.5, y + 0.5)
+        al = []
+        for g in gids:
+            q, h = proj_mod.tangent_coords(d, pre["u"][g], pre["E"][g], pre["f"])
+            al.append(0.0 if h <= 0 else min(params.alpha_max, pre["sigma"][g] * math.exp(-0.5 * q @ pre["C"][g] @ q)))
+        C, T = blend_mod.exhaustive_blend(np.array(al), key[gids], pre["color"][gids],
+                                          params.alpha_min, params.t_min)
+        np.testing.assert_allclose(res["images"][0][:, y, x], np.r_[C, 1 - T], atol=1e-12)
