@@ -44,6 +44,7 @@ typedef struct ihipStream_t* vrs_stream_t; /* hipStream_t */
 #define VRS_ERR_HIP (-3)
 #define VRS_ERR_UNSUPPORTED (-4)
 #define VRS_ERR_SCRATCH (-5) /* request larger than the fixed scratch of a no-allocation entry point */
+#define VRS_ERR_NONFINITE (-6) /* (device) a Gaussian parameter was NaN or infinite; see vrs_preprocess */
 
 /* Limits. */
 #define VRS_MAX_VIEWS 32
@@ -92,15 +93,27 @@ typedef struct {
     int32_t width, height;
 } vrs_camera;
 
-/* Fovea (Sec. 4.3): mask w = clamp((rho (1 + b) - e) / (rho b), 0, 1) of the
- * angle e between a pixel's ray and the ray through center_px, with radius
- * rho = radius_deg and band fraction b = band_frac (the paper uses a 10 %
- * linear band).  enabled = 0 renders the view plainly with 16x16 tiles. */
+/* Fovea (Sec. 4.3): the continuous mask w of the full-resolution centre
+ * region, with band fraction b = band_frac (the paper uses a 10 % linear
+ * band).
+ *   shape VRS_FOVEA_DISC: w = clamp((rho (1 + b) - e) / (rho b), 0, 1) of
+ *     the angle e between a pixel's ray and the ray through center_px, rho =
+ *     radius_deg.
+ *   shape VRS_FOVEA_RECT (the paper's layout, Sec. 5: a centre region of
+ *     half the image with 10 % padding): per axis
+ *     u = clamp((h (1 + b) - |p - c|) / (h b), 0, 1) with half-extent
+ *     h = half_px[axis] and c = center_px[axis], w = min(u_x, u_y).
+ *   Without a band (b = 0) w is the indicator of the disc or rectangle.
+ * enabled = 0 renders the view plainly. */
+#define VRS_FOVEA_DISC 0
+#define VRS_FOVEA_RECT 1
 typedef struct {
     int32_t enabled;
     float center_px[2];
     float radius_deg;
     float band_frac;
+    int32_t shape;
+    float half_px[2];
 } vrs_fovea;
 
 /* Blend schedules (performance only; the output is identical). */
@@ -109,9 +122,16 @@ typedef struct {
                                      quadrant) units longest first from an atomic
                                      counter                                        */
 
+/* Sort key depth (depth_mode). */
+#define VRS_DEPTH_TILE_MAX 0 /* per-tile depth at the splat's maximum point (Sec. 4.2) */
+#define VRS_DEPTH_VIEW_Z 1   /* view-space z of the mean (one depth per Gaussian)    */
+#define VRS_DEPTH_DISTANCE 2 /* distance from the eye to the mean (per Gaussian)     */
+
 /* Renderer knobs.  tile: 16 or 32 for plain views (a 32x32 tile is rendered
  * as four 16x16 subtiles) -- foveated views always use 32x32 sort tiles;
- * window: per-sample resort window length W, 1..32 (Sec. 4.1); blend_batch:
+ * window: per-sample resort window length W, 0..32 (Sec. 4.1; 0 blends in
+ * key order without resorting, like the global-sort comparison renderers of
+ * Sec. 5); depth_mode: one of VRS_DEPTH_* (the key depth); blend_batch:
  * list entries staged per wave and batch, 16, 32 or 64, and schedule, one
  * of VRS_SCHEDULE_* (both performance only, never changing the output).
  * z_near: near cull on camera z; alpha_min: culling and skip threshold
@@ -129,6 +149,7 @@ typedef struct {
     float t_min;
     float dilation;
     float background[3];
+    int32_t depth_mode;
 } vrs_params;
 
 /* Buffer sizes for one configuration (all bytes unless noted). */
@@ -161,10 +182,19 @@ int vrs_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* fovea
  * foveated view, one LOW item per periphery 32x32 tile and one HIGH/HYBRID
  * item per in-image subtile of a split tile; per plain view, one PLAIN item
  * per 16x16 tile.  Synchronises `stream` and returns the exact item count in
- * *n_items.  Classes are decided in FP64. */
+ * *n_items.  Classes are decided in FP64.
+ * Visibility culling (Sec. 4.3, Fig. 5b): vis_masks (may be null) holds per
+ * view a device pointer to a uint8 [height][width] mask (nonzero = visible
+ * through the headset's lens) or null (all visible).  The plan then also
+ * holds, per view, the bitfield of sort tiles with a visible pixel as its
+ * summed-area table (uint32 [nty + 1][ntx + 1]), from which vrs_preprocess
+ * counts and vrs_duplicate enumerates only the visible tiles a splat
+ * covers.  Tiles without a visible pixel get no instances; their pixels are
+ * rendered as background (alpha 0).  The masks are read during the call
+ * only. */
 int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
-                   const vrs_params* p, void* plan, size_t plan_bytes,
-                   uint32_t* n_items, vrs_stream_t stream);
+                   const vrs_params* p, const uint8_t* const* vis_masks, void* plan,
+                   size_t plan_bytes, uint32_t* n_items, vrs_stream_t stream);
 
 /* Per-Gaussian preprocessing (Sec. 3 Eq. 1, Optimal Projection of Sec. 3 end
  * and Sec. 4.2, SH colour; one thread per Gaussian covering every view).
@@ -173,30 +203,43 @@ int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_vi
  * FP64 tile-test record and its colour, and into counts[n_views][n] the number of candidate
  * tiles: the tiles meeting the image of the cone of directions in which the
  * splat can reach alpha_min (a conservative bound; the exact tile test of
- * Eq. 4 runs in vrs_duplicate).  Culled Gaussians (camera z <= z_near,
+ * Eq. 4 runs in vrs_duplicate).  With a plan (from vrs_fovea_plan with the
+ * same cameras, foveas and params; may be null) only the visible tiles of
+ * that rectangle are counted, exactly, from the plan's summed-area table at
+ * the rectangle's corners (Sec. 4.3, Fig. 5b).  Culled Gaussians (camera z <= z_near,
  * opacity < alpha_min, non-finite parameters) get 0.  Sort grids: 32x32 for
- * foveated views, p->tile otherwise. */
+ * foveated views, p->tile otherwise.  A Gaussian with a NaN or infinite
+ * mean, log-scale, quaternion or opacity logit is culled from every view,
+ * and one with a NaN or infinite SH coefficient is coloured black; either
+ * writes VRS_ERR_NONFINITE to *status_dev (if status_dev is not null) while
+ * the frame is still rendered from the other Gaussians. */
 int vrs_preprocess(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
-                   int32_t n_views, const vrs_params* p, void* proj, uint32_t* counts,
-                   int32_t* status_dev, vrs_stream_t stream);
+                   int32_t n_views, const vrs_params* p, const void* plan, void* proj,
+                   uint32_t* counts, int32_t* status_dev, vrs_stream_t stream);
 
 /* Gaussian/tile instantiation (Sec. 3 tile binning; Eq. 4 culling; per-tile
  * depth at the back-projected maximum point, Sec. 4.2).  Exclusive scan of
  * the candidate counts, then one thread per candidate (Gaussian, tile) runs
  * the exact tangent-plane tile test in FP64 and writes, at the candidate's
- * slot (order: view, Gaussian, tile),
+ * slot (order: view, Gaussian, tile; with a plan, the k-th candidate of a
+ * Gaussian is the k-th visible tile of its rectangle in row-major order,
+ * found from the summed-area table; pass the plan given to vrs_preprocess),
  *   keys[c] = (global_tile << 32) | ord(float32(depth)),  gids[c] = Gaussian
  * for a kept instance, or keys[c] = UINT64_MAX (dead) for a culled one;
  * global_tile = view offset + ty*ntx + tx and ord maps float order to
  * unsigned order.  n_inst_dev[0] receives the number of candidates (the
  * capacity needed) and n_inst_dev[1] the number of kept instances.  If the
  * candidates exceed `capacity`, *status_dev = VRS_ERR_CAPACITY and only the
- * first `capacity` slots are written.  `proj`/`counts` come from
- * vrs_preprocess; `ws` must hold sort_ws_bytes. */
+ * first `capacity` slots are written.  If there are 2^32 - 1 candidates or
+ * more (beyond the 32-bit instance offsets), *status_dev =
+ * VRS_ERR_UNSUPPORTED, n_inst_dev[0] = n_inst_dev[1] = 0 and nothing is
+ * written.  `proj`/`counts` come from vrs_preprocess; `ws` must hold
+ * sort_ws_bytes. */
 int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
-                  int32_t n_views, const vrs_params* p, const void* proj, const uint32_t* counts,
-                  uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev,
-                  void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream);
+                  int32_t n_views, const vrs_params* p, const void* plan, const void* proj,
+                  const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
+                  uint32_t* n_inst_dev, void* ws, size_t ws_bytes, int32_t* status_dev,
+                  vrs_stream_t stream);
 
 /* Stable LSD radix sort of (keys, vals) by the low `key_bits` bits of the
  * key (Sec. 3: the instances are sorted).  Equal keys keep their input order,
@@ -236,10 +279,10 @@ int vrs_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity
  * dead keys, so the first n_inst_dev[1] entries of keys/gids are the sorted
  * instances, then vrs_tile_ranges over them. */
 int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
-             int32_t n_views, const vrs_params* p, const void* proj, const uint32_t* counts,
-             uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev,
-             uint32_t* ranges, void* ws, size_t ws_bytes, int32_t* status_dev,
-             vrs_stream_t stream);
+             int32_t n_views, const vrs_params* p, const void* plan, const void* proj,
+             const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
+             uint32_t* n_inst_dev, uint32_t* ranges, void* ws, size_t ws_bytes,
+             int32_t* status_dev, vrs_stream_t stream);
 
 /* Per-tile blending in one launch over every work item of every view (Eq. 2;
  * Sec. 4.1 per-sample resorting with a window of p->window entries; Sec. 4.3
@@ -300,29 +343,87 @@ typedef struct {
 } vrs_gaussian_grads;
 
 /* Workspace bytes of vrs_render_backward: per view and Gaussian, 12 FP32
- * gradients of the render record. */
-size_t vrs_backward_workspace_size(int32_t n, int32_t n_views);
+ * gradients of the render record, and per foveated view three [4][H][W]
+ * FP32 planes (its samples' forward values, dL/d(pre-compose image),
+ * dL/d(sample)).  0 for invalid arguments. */
+size_t vrs_backward_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* foveas,
+                                   int32_t n_views, const vrs_params* p);
 
 /* Gradients of the rendered images (Sec. 4.1 fine-tunes position, rotation,
  * scale, opacity and SH coefficients by backpropagation through the
- * renderer with StopThePop ordering and Optimal Projection).  Plain views
- * only: every fovea must have enabled = 0 (else VRS_ERR_UNSUPPORTED).
- * Inputs: the Gaussians `g`; proj/gids/ranges and rgba[v] from the forward
- * pass (vrs_preprocess, vrs_sort, vrs_render_foveated) with the same
- * cameras, foveas and params; grad_rgba[v] = dL/d(rgba[v]), planar
- * [4][height][width].  The per-sample blending state is recomputed by
+ * renderer with StopThePop ordering and Optimal Projection), for plain and
+ * foveated views.  Inputs: the Gaussians `g`; proj/gids/ranges, the plan
+ * with its n_items and rgba[v] from the forward pass (vrs_fovea_plan,
+ * vrs_preprocess, vrs_sort, vrs_render_foveated) with the same cameras,
+ * foveas and params; grad_rgba[v] = dL/d(rgba[v]), planar
+ * [4][height][width].  Foveated views (rgba[v] is not read): dL/d(rgba) is
+ * carried back through the periphery's blur and nearest-neighbour
+ * upsampling and through the HYBRID mix to the samples, whose blends are
+ * first re-rendered into the workspace (HYBRID samples unmixed).  The per-sample blending state is recomputed by
  * replaying the forward (same entries in the same order, same FP32
  * arithmetic), not stored; a sample's final colour and alpha are read from
  * rgba[v].  Gradients pass through the windowed order as a fixed
  * permutation (a discrete decision), and are zero through a clamped alpha
  * (alpha_max) or a clamped colour (negative SH sum).  Writes every array of
- * `out` (n Gaussians).  `ws` (16-byte aligned) must hold
- * vrs_backward_workspace_size(n, n_views) bytes.  Asynchronous on `stream`. */
+ * `out` (n Gaussians).  `ws` (256-byte aligned) must hold
+ * vrs_backward_workspace_size(n, cams, foveas, n_views, p) bytes.
+ * Asynchronous on `stream`. */
 int vrs_render_backward(const vrs_gaussians* g, const void* proj, const uint32_t* gids,
                         const uint32_t* ranges, const vrs_camera* cams, const vrs_fovea* foveas,
-                        int32_t n_views, const vrs_params* p, const float* const* rgba,
-                        const float* const* grad_rgba, const vrs_gaussian_grads* out, void* ws,
-                        size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream);
+                        int32_t n_views, const vrs_params* p, const void* plan, uint32_t n_items,
+                        const float* const* rgba, const float* const* grad_rgba,
+                        const vrs_gaussian_grads* out, void* ws, size_t ws_bytes,
+                        int32_t* status_dev, vrs_stream_t stream);
+
+/* Two-pass foveated rendering, the comparison baseline of App. A: a centre
+ * pass at full resolution through a tight frustum, a periphery pass at half
+ * resolution, then one blend.  Set-up (host, once per eye configuration):
+ * from the plan that vrs_fovea_plan built for these cameras, foveas and
+ * params, writes per view
+ *   centre_boxes[4v..4v+3] = (x0, y0, x1, y1): the bounding box of the 32x32
+ *     tiles holding a pixel centre with mask w > 0 (x1 == x0: none);
+ *   centre_cams[v]: same pose and focal length, image = that box (principal
+ *     point shifted, horizontal FoV re-derived from the box width);
+ *   low_cams[v]: ceil(W/2) x ceil(H/2), focal length f/2, principal point
+ *     halved, so that low-resolution pixel (i, j) looks along the ray of the
+ *     full-resolution point (2i+1, 2j+1).
+ * The passes are plain renders (fovea disabled, tile 16) of these cameras;
+ * render the periphery with p->dilation / 4 (the same splats in angle).
+ * Copies the class maps to the host: synchronises `stream`. */
+int vrs_two_pass_views(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                       const vrs_params* p, const void* plan, vrs_camera* centre_cams,
+                       int32_t* centre_boxes, vrs_camera* low_cams, vrs_stream_t stream);
+
+/* The blend of the two passes (App. A): per output pixel, the periphery
+ * image upsampled bilinearly between its pixel centres (edge-clamped), and
+ * inside the centre box out = w c + (1 - w) up(low) with the continuous
+ * mask w of the fovea (Sec. 4.3); RGBA alike.  centre_rgba[v] is the centre
+ * pass's [4][y1-y0][x1-x0] image (may be null for views without a box),
+ * low_rgba[v] the periphery pass's [4][ceil(H/2)][ceil(W/2)], out_rgba[v]
+ * [4][H][W].  Asynchronous on `stream`. */
+int vrs_two_pass_compose(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                         const int32_t* centre_boxes, const float* const* centre_rgba,
+                         const float* const* low_rgba, float* const* out_rgba, vrs_stream_t stream);
+
+/* Fine-tuning (Sec. 4.1 fine-tunes a converged model by backpropagation;
+ * Sec. 5: 5K further iterations).  The image loss, read as L1 + L2:
+ *   L = mean |I - I*| + 0.2 mean (I - I*)^2 over the RGB channels of every
+ *   pixel of every view,
+ * written to *loss_dev (device double), and grad_rgba[v] = dL/d(rgba[v])
+ * (RGB (sign(I - I*) + 0.4 (I - I*)) / n, alpha 0), all [4][H][W] planar.
+ * The value is reduced in a fixed order (deterministic).  `ws` (8-byte
+ * aligned) holds vrs_loss_workspace_size(n_views) bytes.  Asynchronous. */
+size_t vrs_loss_workspace_size(int32_t n_views);
+int vrs_loss_l1l2(const vrs_camera* cams, int32_t n_views, const float* const* rgba,
+                  const float* const* target, float* const* grad_rgba, double* loss_dev, void* ws,
+                  size_t ws_bytes, vrs_stream_t stream);
+
+/* One Adam step (bias-corrected, step >= 1) over `count` parameters:
+ * m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+ * param <- param - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * m and v start at zero for step 1.  Asynchronous. */
+int vrs_adam_step(float* param, const float* grad, float* m, float* v, size_t count, float lr,
+                  float beta1, float beta2, float eps, int32_t step, vrs_stream_t stream);
 
 /* Human-readable name of a status code. */
 const char* vrs_status_string(int code);

@@ -14,6 +14,7 @@ VRS_ERR_CAPACITY = -2
 VRS_ERR_HIP = -3
 VRS_ERR_UNSUPPORTED = -4
 VRS_ERR_SCRATCH = -5
+VRS_ERR_NONFINITE = -6
 VRS_SORT_NOALLOC_MAX_PAIRS = 2097152
 VRS_MAX_VIEWS = 32
 VRS_MAX_WINDOW = 32
@@ -44,7 +45,8 @@ class vrs_camera(ctypes.Structure):
 
 class vrs_fovea(ctypes.Structure):
     _fields_ = [("enabled", ctypes.c_int32), ("center_px", ctypes.c_float * 2),
-                ("radius_deg", ctypes.c_float), ("band_frac", ctypes.c_float)]
+                ("radius_deg", ctypes.c_float), ("band_frac", ctypes.c_float),
+                ("shape", ctypes.c_int32), ("half_px", ctypes.c_float * 2)]
 
 
 class vrs_params(ctypes.Structure):
@@ -52,7 +54,7 @@ class vrs_params(ctypes.Structure):
                 ("blend_batch", ctypes.c_int32), ("schedule", ctypes.c_int32), ("z_near", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float),
-                ("background", ctypes.c_float * 3)]
+                ("background", ctypes.c_float * 3), ("depth_mode", ctypes.c_int32)]
 
 
 class vrs_sizes(ctypes.Structure):
@@ -77,18 +79,18 @@ SIGNATURES = {
     "vrs_workspace_size": (_I, [_I, ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I,
                                 ctypes.POINTER(vrs_params), _S, ctypes.POINTER(vrs_sizes)]),
     "vrs_fovea_plan": (_I, [ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I,
-                            ctypes.POINTER(vrs_params), _P, _S, c_u32_p, _P]),
+                            ctypes.POINTER(vrs_params), ctypes.POINTER(ctypes.c_void_p), _P, _S, c_u32_p, _P]),
     "vrs_preprocess": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
-                            ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P]),
+                            ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _P]),
     "vrs_duplicate": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
-                           ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _S,
+                           ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _P, _S,
                            _P, _P, _S, _P, _P]),
     "vrs_sort_pairs": (_I, [_P, _P, _P, _S, _I, _P, _S, _P, _P]),
     "vrs_sort_pairs_workspace_size": (_S, [_S]),
     "vrs_sort_pairs_noalloc": (_I, [_P, _P, _P, _S, _I, _P, _P]),
     "vrs_tile_ranges": (_I, [_P, _P, _S, _U, _P, _P]),
     "vrs_sort": (_I, [ctypes.POINTER(vrs_gaussians), ctypes.POINTER(vrs_camera),
-                      ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _S,
+                      ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _P, _P, _P, _P, _S,
                       _P, _P, _P, _S, _P, _P]),
     "vrs_render_foveated": (_I, [_P, _I, _P, _P, ctypes.POINTER(vrs_camera),
                                  ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _U,
@@ -100,11 +102,23 @@ SIGNATURES = {
                              _P]),
     "vrs_compose": (_I, [ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params),
                          _P, ctypes.POINTER(ctypes.c_void_p), _P, _S, _P]),
-    "vrs_backward_workspace_size": (_S, [_I, _I]),
+    "vrs_backward_workspace_size": (_S, [_I, ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I,
+                                         ctypes.POINTER(vrs_params)]),
     "vrs_render_backward": (_I, [ctypes.POINTER(vrs_gaussians), _P, _P, _P, ctypes.POINTER(vrs_camera),
-                                 ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params),
+                                 ctypes.POINTER(vrs_fovea), _I, ctypes.POINTER(vrs_params), _P, _U,
                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                  ctypes.POINTER(vrs_gaussian_grads), _P, _S, _P, _P]),
+    "vrs_two_pass_views": (_I, [ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I,
+                                ctypes.POINTER(vrs_params), _P, ctypes.POINTER(vrs_camera),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vrs_camera), _P]),
+    "vrs_two_pass_compose": (_I, [ctypes.POINTER(vrs_camera), ctypes.POINTER(vrs_fovea), _I,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _P]),
+    "vrs_loss_workspace_size": (_S, [_I]),
+    "vrs_loss_l1l2": (_I, [ctypes.POINTER(vrs_camera), _I, ctypes.POINTER(ctypes.c_void_p),
+                           ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _P, _P, _S, _P]),
+    "vrs_adam_step": (_I, [_P, _P, _P, _P, _S, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           _I, _P]),
     "vrs_status_string": (ctypes.c_char_p, [_I]),
     "vrs_version": (ctypes.c_char_p, []),
 }
@@ -120,10 +134,18 @@ class VrsError(RuntimeError):
 
 
 def load(path=None):
-    """Load the library once.  Raises if it is missing: there is no fallback."""
+    """Load the library once.  Raises if it is missing: there is no fallback.
+
+    PyTorch is imported first.  Its wheel ships its own HIP runtime, which
+    its libraries name by a different file name than the runtime's soname:
+    loaded before torch, the library would bind the system runtime and torch
+    would then load a second one, and device pointers and streams of one
+    runtime are invalid in the other.  Loaded after torch, the library binds
+    the runtime torch already holds (same soname)."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (binds the HIP runtime the tensors live in)
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(
@@ -174,6 +196,9 @@ def make_fovea(f) -> vrs_fovea:
     o.center_px = (ctypes.c_float * 2)(float(f.center_px[0]), float(f.center_px[1]))
     o.radius_deg = float(f.radius_deg)
     o.band_frac = float(f.band_frac)
+    o.shape = int(getattr(f, "shape", 0))
+    hp = getattr(f, "half_px", (0.0, 0.0))
+    o.half_px = (ctypes.c_float * 2)(float(hp[0]), float(hp[1]))
     return o
 
 
@@ -189,6 +214,7 @@ def make_params(p) -> vrs_params:
     o.t_min = float(p.t_min)
     o.dilation = float(p.dilation)
     o.background = (ctypes.c_float * 3)(*[float(b) for b in p.background])
+    o.depth_mode = int(getattr(p, "depth", 0))
     return o
 
 

@@ -1,7 +1,9 @@
 """Differentiable rendering: a torch.autograd.Function whose forward pass is
-the plain-mode renderer and whose backward pass is vrs_render_backward
-(Sec. 4.1 fine-tunes the Gaussians by backpropagation through the renderer
-with StopThePop ordering and Optimal Projection).
+the renderer (plain and foveated views alike) and whose backward pass is
+vrs_render_backward, through the periphery blur, the LOW group mean and the
+HYBRID mix for foveated views (Sec. 4.1 fine-tunes the Gaussians by
+backpropagation through the renderer with StopThePop ordering and Optimal
+Projection).
 
 The renderer keeps the state of its last forward pass (render records,
 sorted instances, tile ranges) on the GPU, and the backward kernels replay

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvrs.so")
-SOURCES = ["abi.hip", "preprocess.hip", "sort.hip", "fovea.hip", "render.hip", "backward.hip", "noalloc.hip"]
+SOURCES = ["abi.hip", "preprocess.hip", "sort.hip", "fovea.hip", "render.hip", "backward.hip", "noalloc.hip", "twopass.hip", "train.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -10,7 +10,7 @@ namespace vrs {
 int launch_status(hipError_t e) { return e == hipSuccess ? VRS_OK : VRS_ERR_HIP; }
 
 // Launchers defined in the kernel translation units.
-int launch_preprocess(const GaussPtrs&, const GeoViews&, const Knobs&, float*, uint32_t*, hipStream_t);
+int launch_preprocess(const GaussPtrs&, const GeoViews&, const Knobs&, float*, uint32_t*, int*, hipStream_t);
 int launch_duplicate(const GaussPtrs&, const GeoViews&, const Knobs&, const float*, const uint32_t*, uint64_t*,
                      uint32_t*, size_t, uint32_t*, void*, int*, hipStream_t, bool);
 size_t sort_ws_bytes(size_t capacity);
@@ -27,13 +27,13 @@ int launch_blend(const float*, uint32_t, const uint32_t*, const uint32_t*, const
                  int, const RenderViews&, const Knobs&, int, unsigned long long*, hipStream_t);
 uint32_t* order_counter(void* ws);
 int launch_compose(const RenderViews&, const uint8_t*, hipStream_t);
-bool window_supported(int w);
 size_t order_ws_bytes(size_t items_max);
 const uint32_t* launch_order_items(const uint32_t* items, uint32_t n_items, const uint32_t* count_dev,
                                    size_t items_max, const uint32_t* ranges, const RenderViews& views, void* ws,
                                    int* err, hipStream_t s);
 
-int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, void* plan, size_t items_max, hipStream_t s);
+int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, const VisViews& vis, void* plan,
+                      size_t items_max, hipStream_t s);
 }  // namespace vrs
 
 namespace {
@@ -48,6 +48,7 @@ struct ViewLayout {
     uint32_t tile_off;
     uint32_t cls_off;
     size_t pre_off;  // float offset into the render workspace
+    size_t sat_off;  // byte offset of the view's summed-area table in the plan
 };
 
 struct Layout {
@@ -67,8 +68,8 @@ bool finite_f(float x) { return isfinite(x); }
 int check_params(const vrs_params* p) {
     if (!p) return VRS_ERR_INVALID_ARG;
     if (p->tile != 16 && p->tile != 32) return VRS_ERR_INVALID_ARG;
-    if (p->window < 1 || p->window > VRS_MAX_WINDOW) return VRS_ERR_INVALID_ARG;
-    if (!window_supported(p->window)) return VRS_ERR_UNSUPPORTED;
+    if (p->window < 0 || p->window > VRS_MAX_WINDOW) return VRS_ERR_INVALID_ARG;
+    if (p->depth_mode < VRS_DEPTH_TILE_MAX || p->depth_mode > VRS_DEPTH_DISTANCE) return VRS_ERR_INVALID_ARG;
     if (p->blend_batch != 16 && p->blend_batch != 32 && p->blend_batch != 64) return VRS_ERR_UNSUPPORTED;
     if (p->schedule != VRS_SCHEDULE_ONESHOT && p->schedule != VRS_SCHEDULE_PERSISTENT) return VRS_ERR_INVALID_ARG;
     if (!(p->z_near > 0.f) || !finite_f(p->z_near)) return VRS_ERR_INVALID_ARG;
@@ -97,8 +98,16 @@ int make_layout(const vrs_camera* cams, const vrs_fovea* foveas, int n_views, co
         if (!finite_f(c.cx) || !finite_f(c.cy)) return VRS_ERR_INVALID_ARG;
         if (fv.enabled) {
             if (!finite_f(fv.center_px[0]) || !finite_f(fv.center_px[1])) return VRS_ERR_INVALID_ARG;
-            if (!(fv.radius_deg >= 0.f && fv.radius_deg <= 180.f)) return VRS_ERR_INVALID_ARG;
             if (!(fv.band_frac >= 0.f) || !finite_f(fv.band_frac)) return VRS_ERR_INVALID_ARG;
+            if (fv.shape == VRS_FOVEA_DISC) {
+                if (!(fv.radius_deg >= 0.f && fv.radius_deg <= 180.f)) return VRS_ERR_INVALID_ARG;
+            } else if (fv.shape == VRS_FOVEA_RECT) {
+                if (!(fv.half_px[0] >= 0.f) || !(fv.half_px[1] >= 0.f) || !finite_f(fv.half_px[0]) ||
+                    !finite_f(fv.half_px[1]))
+                    return VRS_ERR_INVALID_ARG;
+            } else {
+                return VRS_ERR_INVALID_ARG;
+            }
         }
         ViewLayout& V = L.v[v];
         V.f = (double(c.width) / 2.0) / tan(double(c.fov_x_deg) * (M_PI / 180.0) / 2.0);
@@ -121,7 +130,13 @@ int make_layout(const vrs_camera* cams, const vrs_fovea* foveas, int n_views, co
     L.tiles_total = uint32_t(tiles);
     L.items_max = uint32_t(items);
     L.cls_bytes = size_t(cls);
-    L.plan_bytes = kPlanItemsOff + size_t(items) * 4 + ((size_t(cls) + 255) & ~size_t(255));
+    // Then, per view, the summed-area table of its visible sort tiles.
+    size_t sat = kPlanItemsOff + size_t(items) * 4 + ((size_t(cls) + 255) & ~size_t(255));
+    for (int v = 0; v < n_views; ++v) {
+        L.v[v].sat_off = sat;
+        sat += ((size_t(L.v[v].ntx + 1) * size_t(L.v[v].nty + 1) * sizeof(uint32_t)) + 255) & ~size_t(255);
+    }
+    L.plan_bytes = sat;
     L.render_ws_floats = size_t(pre);
     L.order_off = ((size_t(pre) * sizeof(float)) + 255) & ~size_t(255);
     L.render_ws_bytes = L.order_off + order_ws_bytes(size_t(items));
@@ -155,10 +170,12 @@ Knobs knobs(const vrs_params* p) {
     k.t_min = p->t_min;
     k.dilation = p->dilation;
     for (int c = 0; c < 3; ++c) k.bg[c] = p->background[c];
+    k.window = p->window;
+    k.depth_mode = p->depth_mode;
     return k;
 }
 
-GeoViews geo_views(const vrs_camera* cams, const Layout& L, const vrs_params* p) {
+GeoViews geo_views(const vrs_camera* cams, const Layout& L, const vrs_params* p, const void* plan) {
     GeoViews G;
     memset(&G, 0, sizeof(G));
     G.n = L.n_views;
@@ -180,6 +197,7 @@ GeoViews geo_views(const vrs_camera* cams, const Layout& L, const vrs_params* p)
         o.ntx = V.ntx;
         o.nty = V.nty;
         o.tile_off = V.tile_off;
+        o.sat = plan ? reinterpret_cast<const uint32_t*>(static_cast<const char*>(plan) + V.sat_off) : nullptr;
     }
     return G;
 }
@@ -195,7 +213,8 @@ int key_bits_for(uint32_t tiles_total) {
 }  // namespace
 
 static int duplicate_impl(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
-                          int32_t n_views, const vrs_params* p, const void* proj, const uint32_t* counts,
+                          int32_t n_views, const vrs_params* p, const void* plan, const void* proj,
+                          const uint32_t* counts,
                           uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev, void* ws,
                           size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream, bool count_live) {
     int rc = check_gaussians(g);
@@ -209,7 +228,8 @@ static int duplicate_impl(const vrs_gaussians* g, const vrs_camera* cams, const 
     if (capacity > 0xFFFFFFFFull || nv > 0xFFFFFFFFull) return VRS_ERR_UNSUPPORTED;
     if (ws_bytes < dup_ws_bytes(nv) || !aligned(keys, 8) || !aligned(ws, 16) || !aligned(proj, 16))
         return VRS_ERR_INVALID_ARG;
-    return launch_duplicate(gauss_ptrs(g), geo_views(cams, L, p), knobs(p), static_cast<const float*>(proj), counts,
+    if (plan && !aligned(plan, 256)) return VRS_ERR_INVALID_ARG;
+    return launch_duplicate(gauss_ptrs(g), geo_views(cams, L, p, plan), knobs(p), static_cast<const float*>(proj), counts,
                             keys, gids, capacity, n_inst_dev, ws, status_dev, reinterpret_cast<hipStream_t>(stream),
                             count_live);
 }
@@ -224,6 +244,7 @@ const char* vrs_status_string(int code) {
         case VRS_ERR_HIP: return "VRS_ERR_HIP";
         case VRS_ERR_UNSUPPORTED: return "VRS_ERR_UNSUPPORTED";
         case VRS_ERR_SCRATCH: return "VRS_ERR_SCRATCH";
+        case VRS_ERR_NONFINITE: return "VRS_ERR_NONFINITE";
         default: return "VRS_ERR_UNKNOWN";
     }
 }
@@ -249,16 +270,20 @@ int vrs_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* fovea
 }
 
 int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,
-                   void* plan, size_t plan_bytes, uint32_t* n_items, vrs_stream_t stream) {
+                   const uint8_t* const* vis_masks, void* plan, size_t plan_bytes, uint32_t* n_items,
+                   vrs_stream_t stream) {
     Layout L;
     int rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
     if (!plan || !n_items || plan_bytes < L.plan_bytes || !aligned(plan, 256)) return VRS_ERR_INVALID_ARG;
     FovView fv[VRS_MAX_VIEWS];
     ItemViews iv;
+    VisViews vis;
     memset(fv, 0, sizeof(fv));
     memset(&iv, 0, sizeof(iv));
+    memset(&vis, 0, sizeof(vis));
     iv.n = n_views;
+    vis.n = n_views;
     for (int v = 0; v < n_views; ++v) {
         const ViewLayout& V = L.v[v];
         const vrs_camera& c = cams[v];
@@ -277,6 +302,12 @@ int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_vi
         const double outer = rho * (1.0 + b);
         o.cos_low = outer >= M_PI ? -2.0 : cos(outer);
         o.cos_high = rho >= M_PI ? -2.0 : cos(rho);
+        o.shape = f.shape;
+        o.band = b;
+        o.fc[0] = double(f.center_px[0]);
+        o.fc[1] = double(f.center_px[1]);
+        o.half[0] = double(f.half_px[0]);
+        o.half[1] = double(f.half_px[1]);
         o.W = c.width;
         o.H = c.height;
         o.ntx32 = (c.width + 31) / 32;
@@ -293,9 +324,17 @@ int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_vi
         it.W = c.width;
         it.H = c.height;
         it.cls_off = V.cls_off;
+        VisView& vv = vis.v[v];
+        vv.mask = vis_masks ? vis_masks[v] : nullptr;
+        vv.W = c.width;
+        vv.H = c.height;
+        vv.T = V.T;
+        vv.ntx = V.ntx;
+        vv.nty = V.nty;
+        vv.sat = reinterpret_cast<uint32_t*>(static_cast<char*>(plan) + V.sat_off);
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    rc = launch_fovea_plan(fv, iv, plan, L.items_max, s);
+    rc = launch_fovea_plan(fv, iv, vis, plan, L.items_max, s);
     if (rc != VRS_OK) return rc;
     uint32_t cnt = 0;
     if (hipMemcpyAsync(&cnt, plan, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess) return VRS_ERR_HIP;
@@ -305,24 +344,25 @@ int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_vi
 }
 
 int vrs_preprocess(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
-                   const vrs_params* p, void* proj, uint32_t* counts, int32_t* status_dev, vrs_stream_t stream) {
-    (void)status_dev;
+                   const vrs_params* p, const void* plan, void* proj, uint32_t* counts, int32_t* status_dev,
+                   vrs_stream_t stream) {
     int rc = check_gaussians(g);
     if (rc != VRS_OK) return rc;
     Layout L;
     rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
     if (g->n > 0 && (!proj || !counts || !aligned(proj, 16))) return VRS_ERR_INVALID_ARG;
-    return launch_preprocess(gauss_ptrs(g), geo_views(cams, L, p), knobs(p), static_cast<float*>(proj), counts,
-                             reinterpret_cast<hipStream_t>(stream));
+    if (plan && !aligned(plan, 256)) return VRS_ERR_INVALID_ARG;
+    return launch_preprocess(gauss_ptrs(g), geo_views(cams, L, p, plan), knobs(p), static_cast<float*>(proj), counts,
+                             status_dev, reinterpret_cast<hipStream_t>(stream));
 }
 
 int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
-                  const vrs_params* p, const void* proj, const uint32_t* counts, uint64_t* keys, uint32_t* gids,
-                  size_t capacity, uint32_t* n_inst_dev, void* ws, size_t ws_bytes, int32_t* status_dev,
-                  vrs_stream_t stream) {
-    return duplicate_impl(g, cams, foveas, n_views, p, proj, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
-                          status_dev, stream, true);
+                  const vrs_params* p, const void* plan, const void* proj, const uint32_t* counts, uint64_t* keys,
+                  uint32_t* gids, size_t capacity, uint32_t* n_inst_dev, void* ws, size_t ws_bytes,
+                  int32_t* status_dev, vrs_stream_t stream) {
+    return duplicate_impl(g, cams, foveas, n_views, p, plan, proj, counts, keys, gids, capacity, n_inst_dev, ws,
+                          ws_bytes, status_dev, stream, true);
 }
 
 size_t vrs_sort_pairs_workspace_size(size_t capacity) { return sort_ws_bytes(capacity); }
@@ -345,8 +385,8 @@ int vrs_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity
 }
 
 int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
-             const vrs_params* p, const void* proj, const uint32_t* counts, uint64_t* keys, uint32_t* gids,
-             size_t capacity, uint32_t* n_inst_dev, uint32_t* ranges, void* ws, size_t ws_bytes,
+             const vrs_params* p, const void* plan, const void* proj, const uint32_t* counts, uint64_t* keys,
+             uint32_t* gids, size_t capacity, uint32_t* n_inst_dev, uint32_t* ranges, void* ws, size_t ws_bytes,
              int32_t* status_dev, vrs_stream_t stream) {
     Layout L;
     int rc = make_layout(cams, foveas, n_views, p, L);
@@ -354,8 +394,8 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
     if (!ranges && L.tiles_total > 0) return VRS_ERR_INVALID_ARG;
     if (capacity > 0 && ws_bytes < sort_ws_bytes(capacity)) return VRS_ERR_INVALID_ARG;
     // The sort's first kernel counts the kept instances into n_inst_dev[1].
-    rc = duplicate_impl(g, cams, foveas, n_views, p, proj, counts, keys, gids, capacity, n_inst_dev, ws, ws_bytes,
-                        status_dev, stream, false);
+    rc = duplicate_impl(g, cams, foveas, n_views, p, plan, proj, counts, keys, gids, capacity, n_inst_dev, ws,
+                        ws_bytes, status_dev, stream, false);
     if (rc != VRS_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (capacity > 0) {
@@ -370,6 +410,23 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
 }  // extern "C"
 
 namespace {
+
+// One view's table for the render kernels.
+void fill_render_view(RenderView& o, const ViewLayout& V, const vrs_camera& c, const vrs_fovea& f, float* out,
+                      float* pre) {
+    memset(&o, 0, sizeof(o));
+    o.out = out;
+    o.pre = pre;
+    o.mask = make_fov_mask(c, f);
+    o.W = c.width;
+    o.H = c.height;
+    o.T = V.T;
+    o.ntx = V.ntx;
+    o.ntx16 = V.ntx16;
+    o.tile_off = V.tile_off;
+    o.cls_off = V.cls_off;
+    o.foveated = uint8_t(V.foveated);
+}
 
 // Shared argument checks and tables of the render entry points.
 int render_setup(int32_t n, const void* proj, const uint32_t* gids, const uint32_t* ranges, const vrs_camera* cams,
@@ -386,31 +443,9 @@ int render_setup(int32_t n, const void* proj, const uint32_t* gids, const uint32
     R.n = n_views;
     for (int v = 0; v < n_views; ++v) {
         const ViewLayout& V = L.v[v];
-        const vrs_camera& c = cams[v];
-        const vrs_fovea& f = foveas[v];
-        RenderView& o = R.v[v];
         if (!rgba[v]) return VRS_ERR_INVALID_ARG;
-        o.out = rgba[v];
-        o.pre = V.foveated ? static_cast<float*>(ws) + V.pre_off : rgba[v];
-        o.f = float(V.f);
-        o.cx = c.cx;
-        o.cy = c.cy;
-        const double d0 = (double(f.center_px[0]) - double(c.cx)) / V.f;
-        const double d1 = (double(f.center_px[1]) - double(c.cy)) / V.f;
-        const double dn = sqrt(d0 * d0 + d1 * d1 + 1.0);
-        o.fdir[0] = float(d0 / dn);
-        o.fdir[1] = float(d1 / dn);
-        o.fdir[2] = float(1.0 / dn);
-        o.rho = float(double(f.radius_deg) * (M_PI / 180.0));
-        o.band = f.band_frac;
-        o.W = c.width;
-        o.H = c.height;
-        o.T = V.T;
-        o.ntx = V.ntx;
-        o.ntx16 = V.ntx16;
-        o.tile_off = V.tile_off;
-        o.cls_off = V.cls_off;
-        o.foveated = V.foveated;
+        fill_render_view(R.v[v], V, cams[v], foveas[v], rgba[v],
+                         V.foveated ? static_cast<float*>(ws) + V.pre_off : rgba[v]);
     }
     return VRS_OK;
 }
@@ -489,64 +524,121 @@ int vrs_render_foveated(const void* proj, int32_t n, const uint32_t* gids, const
 namespace vrs {
 size_t backward_ws_bytes(size_t n, int n_views);
 int launch_backward(const GaussPtrs&, const GeoViews&, const float*, const uint32_t*, const uint32_t*,
-                    const BwdViews&, const Knobs&, int, float*, const GradPtrs&, hipStream_t);
+                    const uint32_t*, uint32_t, const BwdViews&, const Knobs&, int, float*, const GradPtrs&,
+                    hipStream_t);
+int launch_fov_grads(const FovGradView& V, hipStream_t s);
 }  // namespace vrs
+
+namespace {
+
+// Backward workspace: the per-view render-record gradients, then for every
+// foveated view three [4][H][W] float planes: its samples' forward values
+// (HYBRID unmixed), dL/d(pre-compose image) and dL/d(sample).
+size_t bwd_fov_off(size_t n, int n_views) { return (backward_ws_bytes(n, n_views) + 255) & ~size_t(255); }
+
+size_t bwd_ws_total(size_t n, const vrs_camera* cams, const vrs_fovea* foveas, int n_views) {
+    size_t b = bwd_fov_off(n, n_views);
+    for (int v = 0; v < n_views; ++v)
+        if (foveas[v].enabled) b += 3 * 4 * size_t(cams[v].width) * size_t(cams[v].height) * sizeof(float);
+    return b;
+}
+
+}  // namespace
 
 extern "C" {
 
-size_t vrs_backward_workspace_size(int32_t n, int32_t n_views) {
-    if (n < 0 || n_views < 0) return 0;
-    return vrs::backward_ws_bytes(size_t(n), n_views);
+size_t vrs_backward_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views,
+                                   const vrs_params* p) {
+    Layout L;
+    if (n < 0 || make_layout(cams, foveas, n_views, p, L) != VRS_OK) return 0;
+    return bwd_ws_total(size_t(n), cams, foveas, n_views);
 }
 
 int vrs_render_backward(const vrs_gaussians* g, const void* proj, const uint32_t* gids, const uint32_t* ranges,
                         const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_views, const vrs_params* p,
-                        const float* const* rgba, const float* const* grad_rgba, const vrs_gaussian_grads* out,
-                        void* ws, size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream) {
+                        const void* plan, uint32_t n_items, const float* const* rgba,
+                        const float* const* grad_rgba, const vrs_gaussian_grads* out, void* ws, size_t ws_bytes,
+                        int32_t* status_dev, vrs_stream_t stream) {
     (void)status_dev;
     int rc = check_gaussians(g);
     if (rc != VRS_OK) return rc;
     Layout L;
     rc = make_layout(cams, foveas, n_views, p, L);
     if (rc != VRS_OK) return rc;
-    for (int v = 0; v < n_views; ++v)
-        if (foveas[v].enabled) return VRS_ERR_UNSUPPORTED;
-    if (!rgba || !grad_rgba || !out) return VRS_ERR_INVALID_ARG;
+    if (!rgba || !grad_rgba || !out || !plan || !aligned(plan, 256) || n_items > L.items_max)
+        return VRS_ERR_INVALID_ARG;
+    bool any_fov = false;
+    for (int v = 0; v < n_views; ++v) any_fov = any_fov || foveas[v].enabled;
     if (g->n > 0) {
         if (!proj || !gids || !ranges || !aligned(proj, 16)) return VRS_ERR_INVALID_ARG;
         if (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh)
             return VRS_ERR_INVALID_ARG;
-        if (!ws || !aligned(ws, 16) || ws_bytes < backward_ws_bytes(size_t(g->n), n_views))
+        if (!ws || !aligned(ws, 256) || ws_bytes < bwd_ws_total(size_t(g->n), cams, foveas, n_views))
             return VRS_ERR_INVALID_ARG;
     }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint32_t* items = plan_items(plan);
     BwdViews B;
     memset(&B, 0, sizeof(B));
     B.n = n_views;
-    uint32_t items = 0;
+    RenderViews R;
+    memset(&R, 0, sizeof(R));
+    R.n = n_views;
+    float* fov_ws = reinterpret_cast<float*>(static_cast<char*>(ws) + bwd_fov_off(size_t(g->n), n_views));
     for (int v = 0; v < n_views; ++v) {
-        if (!rgba[v] || !grad_rgba[v]) return VRS_ERR_INVALID_ARG;
+        if (!grad_rgba[v] || (!foveas[v].enabled && !rgba[v])) return VRS_ERR_INVALID_ARG;
         const ViewLayout& V = L.v[v];
         BwdView& o = B.v[v];
-        o.rgba = rgba[v];
-        o.grad = grad_rgba[v];
         o.W = cams[v].width;
         o.H = cams[v].height;
         o.T = V.T;
         o.ntx = V.ntx;
         o.tile_off = V.tile_off;
-        o.item_off = items;
-        items += uint32_t(V.ntx * V.nty) * (V.T == 32 ? 4u : 1u);
+        RenderView& r = R.v[v];
+        fill_render_view(r, V, cams[v], foveas[v], nullptr, nullptr);
+        if (!foveas[v].enabled || g->n == 0) {
+            o.rgba = rgba[v];
+            o.grad = grad_rgba[v];
+            r.skip = 1;
+            continue;
+        }
+        const size_t plane = size_t(o.W) * size_t(o.H);
+        float* cfin = fov_ws;
+        float* gpre = cfin + 4 * plane;
+        float* gsamp = gpre + 4 * plane;
+        fov_ws = gsamp + 4 * plane;
+        o.rgba = cfin;
+        o.grad = gsamp;
+        r.out = cfin;
+        r.pre = cfin;
+        r.nomix = 1;
+        FovGradView F;
+        F.gout = grad_rgba[v];
+        F.gpre = gpre;
+        F.gsamp = gsamp;
+        F.cls = plan_classes(plan, L) + V.cls_off;
+        F.W = o.W;
+        F.H = o.H;
+        F.ntx16 = V.ntx16;
+        F.mask = make_fov_mask(cams[v], foveas[v]);
+        rc = launch_fov_grads(F, s);
+        if (rc != VRS_OK) return rc;
     }
-    B.items_total = items;
+    if (any_fov && g->n > 0 && n_items > 0) {
+        // The foveated views' samples as the forward blended them (HYBRID
+        // samples unmixed), into the workspace; plain views are skipped.
+        rc = launch_blend(static_cast<const float*>(proj), uint32_t(g->n), gids, ranges, items, n_items, nullptr,
+                          p->blend_batch, VRS_SCHEDULE_ONESHOT, R, knobs(p), p->window, nullptr, s);
+        if (rc != VRS_OK) return rc;
+    }
     GradPtrs G;
     G.means = out->means;
     G.log_scales = out->log_scales;
     G.quats = out->quats;
     G.opac = out->opacity_logits;
     G.sh = out->sh;
-    return launch_backward(gauss_ptrs(g), geo_views(cams, L, p), static_cast<const float*>(proj), gids, ranges, B,
-                           knobs(p), p->window, static_cast<float*>(ws), G,
-                           reinterpret_cast<hipStream_t>(stream));
+    return launch_backward(gauss_ptrs(g), geo_views(cams, L, p, nullptr), static_cast<const float*>(proj), gids,
+                           ranges, items, n_items, B, knobs(p), p->window, static_cast<float*>(ws), G, s);
 }
 
 }  // extern "C"

@@ -69,10 +69,11 @@ struct BWindow {
     float t[W], a[W];
     uint32_t k[W];
 
-    __device__ inline void init() {
+    // w <= W real slots, as the forward window (k_render's Window::init).
+    __device__ inline void init(int w) {
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            t[i] = -FLT_MAX;
+            t[i] = i < w ? -FLT_MAX : FLT_MAX;
             a[i] = 0.f;
             k[i] = kNone;
         }
@@ -166,33 +167,46 @@ constexpr int kQueueGo = kQueue - 63;  // a round runs once this many are queued
 template <int W>
 __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restrict__ proj, uint32_t n_gauss,
                                                             const uint32_t* __restrict__ gids,
-                                                            const uint32_t* __restrict__ ranges, BwdViews views,
+                                                            const uint32_t* __restrict__ ranges,
+                                                            const uint32_t* __restrict__ items, BwdViews views,
                                                             Knobs kn, float* __restrict__ grad2d) {
-    __shared__ float4 ring[kRing][6];
+    // Field-major: the lanes of a queue round read field k of different
+    // entries, 16 bytes apart rather than an entry's 96 bytes apart, which
+    // spreads them over the LDS banks.
+    __shared__ float4 ring[6][kRing];
     // Value-major, so that the lanes of one atomic instruction (one value of
     // different entries) fall in different banks.
     __shared__ unsigned long long acc[kG][kRing];
     __shared__ int acc_scale[kG][kRing];
     __shared__ float4 queue[kBwdThreads / 64][kQueue];
 
-    const uint32_t item = blockIdx.x;
-    int v = 0;
-    while (v + 1 < views.n && item >= views.v[v + 1].item_off) ++v;
+    // The work item (the plan's, as rendered by the forward pass).
+    const uint32_t item = items[blockIdx.x];
+    const int v = item_view(item);
+    const bool low = item_class(item) == VRS_CLASS_LOW;
+    const int sub = item_sub(item);
+    const uint32_t tile = item_tile(item);
     const BwdView& V = views.v[v];
     const int T = V.T;
-    const uint32_t local = item - V.item_off;
-    const uint32_t tile = (T == 32) ? local >> 2 : local;
-    const int sub = (T == 32) ? int(local & 3u) : 0;
     const int tx = int(tile % uint32_t(V.ntx)), ty = int(tile / uint32_t(V.ntx));
     const int ox = tx * T, oy = ty * T;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // Sample of a lane of this wave: as in the forward, wave wv owns the 8x8
-    // quadrant (qx, qy) of the 16x16 samples, lanes 4q..4q+3 a 2x2 group.
-    const int bx = (T == 32) ? (sub & 1) * 16 : 0, by = (T == 32) ? (sub >> 1) * 16 : 0;
+    // quadrant (qx, qy) of the 16x16 samples -- pixels of a (sub)tile, lanes
+    // 4q..4q+3 a 2x2 group, or the centres of a LOW tile's 2x2 groups.
+    const int bx = (T == 32 && !low) ? (sub & 1) * 16 : 0, by = (T == 32 && !low) ? (sub >> 1) * 16 : 0;
     const int qx = wv & 1, qy = wv >> 1;
     auto sample_of = [&](int l, float& sx_, float& sy_, int& px_, int& py_) {
+        if (low) {
+            const int gx = 8 * qx + (l & 7), gy = 8 * qy + (l >> 3);
+            px_ = ox + 2 * gx;
+            py_ = oy + 2 * gy;
+            sx_ = float(2 * gx + 1);
+            sy_ = float(2 * gy + 1);
+            return;
+        }
         const int qd = l >> 2, kq = l & 3;
         const int lx = 8 * qx + 2 * (qd & 3) + (kq & 1), ly = 8 * qy + 2 * (qd >> 2) + (kq >> 1);
         px_ = ox + bx + lx;
@@ -224,7 +238,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     float D = 0.f;  // g_rgb . (colour accumulated so far)
     bool alive = inimg;
     BWindow<W> win;
-    win.init();
+    win.init(kn.window);
     const float amax = kn.alpha_max, tmin = kn.t_min;
 
     const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
@@ -232,8 +246,11 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
     const float4* vcol = colour_array(proj, size_t(views.n) * size_t(n_gauss)) + size_t(v) * size_t(n_gauss);
     float* vgrad = grad2d + size_t(v) * size_t(n_gauss) * kG;
-    const float rx0 = float(ox + bx + 8 * qx) + 0.5f, rx1 = float(ox + bx + 8 * qx) + 7.5f;
-    const float ry0 = float(oy + by + 8 * qy) + 0.5f, ry1 = float(oy + by + 8 * qy) + 7.5f;
+    // This wave's sample rectangle, for the per-wave box culling of the forward.
+    const float rx0 = low ? float(ox + 16 * qx + 1) : float(ox + bx + 8 * qx) + 0.5f;
+    const float rx1 = low ? float(ox + 16 * qx + 15) : float(ox + bx + 8 * qx) + 7.5f;
+    const float ry0 = low ? float(oy + 16 * qy + 1) : float(oy + by + 8 * qy) + 0.5f;
+    const float ry1 = low ? float(oy + 16 * qy + 15) : float(oy + by + 8 * qy) + 7.5f;
     uint32_t ring_lo = 0;  // smallest arrival index whose record is still in the ring
 
     // An emission (a blended (sample, entry) pair) is completed in three
@@ -304,7 +321,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             float4 e[6];
             if (in_ring) {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) e[k] = ring[sl][k];
+                for (int k = 0; k < 6; ++k) e[k] = ring[k][sl];
             } else {
                 const uint32_t gid = gids[rg.x + ek];
                 stage_entry(reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec), gid, ox, oy, e);
@@ -370,7 +387,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         if (valid) {
             const bool in_ring = ek >= ring_lo;
             const uint32_t gid =
-                in_ring ? __float_as_uint(ring[ek % uint32_t(kRing)][5].z) : gids[rg.x + ek];
+                in_ring ? __float_as_uint(ring[5][ek % uint32_t(kRing)].z) : gids[rg.x + ek];
             pc = bwd_colour(vcol, gid);
             pend = true;
             p_T = Tc;
@@ -400,7 +417,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
                 const int s = base + w / kG, k = w % kG;
                 const int sc = acc_scale[k][s];
                 if (sc != kUnset && acc[k][s] != 0ull)
-                    unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[s][5].z)) * kG + k],
+                    unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[5][s].z)) * kG + k],
                                     fixed_value(acc[k][s], sc));
             }
             __syncthreads();
@@ -411,7 +428,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             float4 e[6];
             stage_entry(reinterpret_cast<const float4*>(vproj + size_t(gid) * kRec), gid, ox, oy, e);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) ring[base + t][k] = e[k];
+            for (int k = 0; k < 6; ++k) ring[k][base + t] = e[k];
         }
         for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
             acc[w % kG][base + w / kG] = 0ull;
@@ -432,8 +449,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         while (todo) {
             const int j = __builtin_ctzll(todo);
             todo &= todo - 1;
-            const float4* st = ring[base + j];
-            const float4 f0 = st[0], f1 = st[1], f2 = st[2];
+            const float4 f0 = ring[0][base + j], f1 = ring[1][base + j], f2 = ring[2][base + j];
             const float dx = f0.x + sx, dy = f0.y + sy;
             const float z1 = fmaf(f0.z, dx, f0.w * dy);
             const float z2 = fmaf(f1.x, dx, f1.y * dy);
@@ -442,7 +458,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             const float h2 = h * h;
             const bool pass = alive && (h > 0.f) && (q <= f2.y * h2);
             if (__ballot(pass) != 0ull) {  // wave-uniform
-                const float4 f3 = st[3], f4 = st[4], f5 = st[5];
+                const float4 f3 = ring[3][base + j], f4 = ring[4][base + j], f5 = ring[5][base + j];
                 const float xa =
                     pass ? fminf(amax, __builtin_amdgcn_exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2))) : 0.f;
                 const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
@@ -481,7 +497,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         if (a >= staged_end) continue;
         const int sc = acc_scale[k][s];
         if (sc != kUnset && acc[k][s] != 0ull)
-            unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[s][5].z)) * kG + k], fixed_value(acc[k][s], sc));
+            unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[5][s].z)) * kG + k], fixed_value(acc[k][s], sc));
     }
 }
 
@@ -780,28 +796,104 @@ __global__ void __launch_bounds__(256) k_fill_f32(float* __restrict__ p, size_t 
 
 size_t backward_ws_bytes(size_t n, int n_views) { return n * size_t(n_views) * kG * sizeof(float); }
 
+// ---------------------------------------------------------------------------
+// Foveated views: dL/d(final image) back through the periphery blur and the
+// nearest-neighbour upsampling, and through the HYBRID mix (Sec. 4.3), to
+// the samples, deterministically (gathers, no atomics).
+// ---------------------------------------------------------------------------
+__device__ inline uint8_t fov_class(const FovGradView& V, int x, int y) {
+    return V.cls[size_t(y >> 4) * V.ntx16 + (x >> 4)];
+}
+
+// dL/d(pre)[q] = dL/d(final)[q] if q is not LOW, plus, for every LOW pixel p
+// whose edge-clamped 3x3 window reads q, K(delta) dL/d(final)[p] summed
+// over the offsets delta that land on q.  One thread per pixel q.
+__global__ void __launch_bounds__(256) k_fov_grad_pre(FovGradView V) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= V.W || y >= V.H) return;
+    const size_t plane = size_t(V.W) * V.H, q = size_t(y) * V.W + x;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (fov_class(V, x, y) != VRS_CLASS_LOW)
+        for (int c = 0; c < 4; ++c) acc[c] = V.gout[c * plane + q];
+    for (int py = max(y - 1, 0); py <= min(y + 1, V.H - 1); ++py)
+        for (int px = max(x - 1, 0); px <= min(x + 1, V.W - 1); ++px) {
+            if (fov_class(V, px, py) != VRS_CLASS_LOW) continue;
+            float w = 0.f;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int sx = min(max(px + dx, 0), V.W - 1), sy = min(max(py + dy, 0), V.H - 1);
+                    if (sx == x && sy == y) w += float((2 - dx * dx) * (2 - dy * dy)) * (1.f / 16.f);
+                }
+            const size_t p = size_t(py) * V.W + px;
+            for (int c = 0; c < 4; ++c) acc[c] = fmaf(w, V.gout[c * plane + p], acc[c]);
+        }
+    for (int c = 0; c < 4; ++c) V.gpre[c * plane + q] = acc[c];
+}
+
+// dL/d(sample): a HIGH pixel's is dL/d(pre); a HYBRID pixel q's is
+// w_q dL/d(pre)[q] + sum over its 2x2 group's in-image pixels p of
+// (1 - w_p) / n dL/d(pre)[p]; a LOW group's (at its top-left pixel) is the
+// sum of dL/d(pre) over its in-image pixels.
+__global__ void __launch_bounds__(256) k_fov_grad_samples(FovGradView V) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= V.W || y >= V.H) return;
+    const size_t plane = size_t(V.W) * V.H, q = size_t(y) * V.W + x;
+    const uint8_t k = fov_class(V, x, y);
+    const int gx = x & ~1, gy = y & ~1;
+    const int gx1 = min(gx + 1, V.W - 1), gy1 = min(gy + 1, V.H - 1);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (k == VRS_CLASS_LOW) {
+        if (x != gx || y != gy) return;  // only the group's top-left pixel holds its sample
+        for (int yy = gy; yy <= gy1; ++yy)
+            for (int xx = gx; xx <= gx1; ++xx)
+                for (int c = 0; c < 4; ++c) acc[c] += V.gpre[c * plane + size_t(yy) * V.W + xx];
+    } else if (k == VRS_CLASS_HYBRID) {
+        const float n = float((gx1 - gx + 1) * (gy1 - gy + 1));
+        const float wq = fovea_weight(V.mask, x, y);
+        for (int c = 0; c < 4; ++c) acc[c] = wq * V.gpre[c * plane + q];
+        for (int yy = gy; yy <= gy1; ++yy)
+            for (int xx = gx; xx <= gx1; ++xx) {
+                const float f = (1.f - fovea_weight(V.mask, xx, yy)) / n;
+                for (int c = 0; c < 4; ++c) acc[c] = fmaf(f, V.gpre[c * plane + size_t(yy) * V.W + xx], acc[c]);
+            }
+    } else {
+        for (int c = 0; c < 4; ++c) acc[c] = V.gpre[c * plane + q];
+    }
+    for (int c = 0; c < 4; ++c) V.gsamp[c * plane + q] = acc[c];
+}
+
+int launch_fov_grads(const FovGradView& V, hipStream_t s) {
+    const dim3 grid((V.W + 63) / 64, (V.H + 3) / 4);
+    hipLaunchKernelGGL(k_fov_grad_pre, grid, dim3(256), 0, s, V);
+    hipLaunchKernelGGL(k_fov_grad_samples, grid, dim3(256), 0, s, V);
+    return launch_status(hipGetLastError());
+}
+
 template <int W>
 static void launch_render_bwd(const float* proj, uint32_t n, const uint32_t* gids, const uint32_t* ranges,
-                              const BwdViews& views, const Knobs& kn, float* grad2d, hipStream_t s) {
-    hipLaunchKernelGGL(k_render_bwd<W>, dim3(views.items_total), dim3(kBwdThreads), 0, s, proj, n, gids, ranges,
+                              const uint32_t* items, uint32_t n_items, const BwdViews& views, const Knobs& kn,
+                              float* grad2d, hipStream_t s) {
+    hipLaunchKernelGGL(k_render_bwd<W>, dim3(n_items), dim3(kBwdThreads), 0, s, proj, n, gids, ranges, items,
                        views, kn, grad2d);
 }
 
 int launch_backward(const GaussPtrs& g, const GeoViews& gv, const float* proj, const uint32_t* gids,
-                    const uint32_t* ranges, const BwdViews& views, const Knobs& kn, int window, float* grad2d,
-                    const GradPtrs& out, hipStream_t s) {
+                    const uint32_t* ranges, const uint32_t* items, uint32_t n_items, const BwdViews& views,
+                    const Knobs& kn, int window, float* grad2d, const GradPtrs& out, hipStream_t s) {
     const size_t ng = size_t(g.n) * size_t(views.n) * kG;
     if (ng > 0) {
         const size_t blocks = (ng + 255) / 256;
         hipLaunchKernelGGL(k_fill_f32, dim3(unsigned(blocks < 16384 ? blocks : 16384)), dim3(256), 0, s, grad2d,
                            ng);
     }
-    if (views.items_total > 0 && g.n > 0) {
-#define VRS_BWD_W(w)                                                                    \
-    case w:                                                                             \
-        launch_render_bwd<w>(proj, uint32_t(g.n), gids, ranges, views, kn, grad2d, s); \
+    if (n_items > 0 && g.n > 0) {
+#define VRS_BWD_W(w)                                                                                      \
+    case w:                                                                                               \
+        launch_render_bwd<w>(proj, uint32_t(g.n), gids, ranges, items, n_items, views, kn, grad2d, s); \
         break;
-        switch (window) {
+        switch (window_network(window)) {
             VRS_BWD_W(1) VRS_BWD_W(2) VRS_BWD_W(3) VRS_BWD_W(4) VRS_BWD_W(6) VRS_BWD_W(8) VRS_BWD_W(12)
             VRS_BWD_W(16) VRS_BWD_W(24) VRS_BWD_W(32)
             default: return VRS_ERR_UNSUPPORTED;

@@ -5,15 +5,39 @@
 // the compact list of render work items, whose length is the exact number of
 // blocks the render launch needs.
 //
-// The mask depends on the angle e between a pixel's ray and the fovea-centre
-// ray: w = 0 iff e >= rho (1 + b), w = 1 iff e <= rho.  Both tests are made
-// on cos(e) in FP64 against host-computed cosines, so classes are decided far
-// more precisely than the float32 inputs.
+// Disc fovea: the mask depends on the angle e between a pixel's ray and the
+// fovea-centre ray: w = 0 iff e >= rho (1 + b), w = 1 iff e <= rho.  Both
+// tests are made on cos(e) in FP64 against host-computed cosines, so classes
+// are decided far more precisely than the float32 inputs.  Rectangle fovea
+// (the paper's layout): the weight itself is evaluated in FP64, operation by
+// operation as the definition writes it.
+//
+// Visibility culling (Sec. 4.3, Fig. 5b): per view, the bitfield of sort
+// tiles holding a visible pixel of the headset's mask, stored as its
+// summed-area table.
 #include "vrs_internal.h"
 
 namespace vrs {
 
 constexpr uint8_t kSubNone = 255;
+
+// Rectangle mask weight (FP64): per axis clamp((h (1 + b) - |p - c|) / (h b), 0, 1),
+// the smaller of the two; the indicator of the closed rectangle without a band.
+__device__ inline double rect_weight(const FovView& V, double px, double py) {
+#pragma clang fp contract(off)
+    double w = 1.0;
+    const double p[2] = {px, py};
+    for (int a = 0; a < 2; ++a) {
+        const double d = fabs(p[a] - V.fc[a]);
+        const double h = V.half[a];
+        double u;
+        if (!(h > 0.0)) u = 0.0;
+        else if (!(V.band > 0.0)) u = d <= h ? 1.0 : 0.0;
+        else u = fmin(fmax((h * (1.0 + V.band) - d) / (h * V.band), 0.0), 1.0);
+        w = fmin(w, u);
+    }
+    return w;
+}
 
 // One block per 32x32 tile of a foveated view: 256 threads x 4 pixels.
 __global__ void __launch_bounds__(256) k_fovea_classes(FovView V, uint8_t* __restrict__ cls) {
@@ -31,13 +55,20 @@ __global__ void __launch_bounds__(256) k_fovea_classes(FovView V, uint8_t* __res
         const int x = tx * 32 + lx, y = ty * 32 + ly;
         if (x >= V.W || y >= V.H) continue;
         const int sub = (lx >> 4) + 2 * (ly >> 4);
-        const double d0 = (double(x) + 0.5 - V.cx) / V.f;
-        const double d1 = (double(y) + 0.5 - V.cy) / V.f;
-        const double dn = sqrt(d0 * d0 + d1 * d1 + 1.0);
-        double c = (d0 * V.dc[0] + d1 * V.dc[1] + V.dc[2]) / (dn * V.dcn);
-        c = fmin(fmax(c, -1.0), 1.0);
-        const bool pos = !V.all_low && !(c <= V.cos_low);
-        const bool one = !V.all_low && (c >= V.cos_high);
+        bool pos, one;
+        if (V.shape == VRS_FOVEA_RECT) {
+            const double w = rect_weight(V, double(x) + 0.5, double(y) + 0.5);
+            pos = w > 0.0;
+            one = w >= 1.0;
+        } else {
+            const double d0 = (double(x) + 0.5 - V.cx) / V.f;
+            const double d1 = (double(y) + 0.5 - V.cy) / V.f;
+            const double dn = sqrt(d0 * d0 + d1 * d1 + 1.0);
+            double c = (d0 * V.dc[0] + d1 * V.dc[1] + V.dc[2]) / (dn * V.dcn);
+            c = fmin(fmax(c, -1.0), 1.0);
+            pos = !V.all_low && !(c <= V.cos_low);
+            one = !V.all_low && (c >= V.cos_high);
+        }
         if (pos) atomicOr(&any_pos, 1);
         if (!one) atomicOr(&not_one[sub], 1);
         atomicOr(&present[sub], 1);
@@ -115,8 +146,53 @@ __global__ void __launch_bounds__(1024) k_fovea_items(ItemViews views, const uin
     if (t == 0) *count = carry;
 }
 
-int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, void* plan, size_t items_max,
-                      hipStream_t s) {
+// One block per sort tile of a view: the tile's bit (some pixel visible, or
+// no mask) goes to the interior of the summed-area table, S[ty + 1][tx + 1].
+__global__ void __launch_bounds__(256) k_vis_tiles(VisView V) {
+    const int tile = blockIdx.x;
+    const int tx = tile % V.ntx, ty = tile / V.ntx;
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    if (!V.mask) {
+        if (threadIdx.x == 0) any = 1;
+    } else {
+        for (int p = threadIdx.x; p < V.T * V.T; p += 256) {
+            const int x = tx * V.T + p % V.T, y = ty * V.T + p / V.T;
+            if (x < V.W && y < V.H && V.mask[size_t(y) * V.W + x] != 0) any = 1;  // benign race: all write 1
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) V.sat[size_t(ty + 1) * (V.ntx + 1) + tx + 1] = any ? 1u : 0u;
+}
+
+// One block per view: zero the table's first row and column, then prefix
+// sums along the rows, then along the columns.
+__global__ void __launch_bounds__(1024) k_vis_sat(VisViews views) {
+    const VisView& V = views.v[blockIdx.x];
+    const int st = V.ntx + 1;
+    for (int x = threadIdx.x; x < st; x += blockDim.x) V.sat[x] = 0u;
+    for (int y = threadIdx.x; y < V.nty + 1; y += blockDim.x) V.sat[size_t(y) * st] = 0u;
+    __syncthreads();
+    for (int y = 1 + threadIdx.x; y <= V.nty; y += blockDim.x) {
+        uint32_t run = 0;
+        for (int x = 1; x <= V.ntx; ++x) {
+            run += V.sat[size_t(y) * st + x];
+            V.sat[size_t(y) * st + x] = run;
+        }
+    }
+    __syncthreads();
+    for (int x = 1 + threadIdx.x; x <= V.ntx; x += blockDim.x) {
+        uint32_t run = 0;
+        for (int y = 1; y <= V.nty; ++y) {
+            run += V.sat[size_t(y) * st + x];
+            V.sat[size_t(y) * st + x] = run;
+        }
+    }
+}
+
+int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, const VisViews& vis, void* plan,
+                      size_t items_max, hipStream_t s) {
     uint32_t* count = static_cast<uint32_t*>(plan);
     uint32_t* items = reinterpret_cast<uint32_t*>(static_cast<char*>(plan) + kPlanItemsOff);
     uint8_t* cls = reinterpret_cast<uint8_t*>(items + items_max);
@@ -126,6 +202,9 @@ int launch_fovea_plan(const FovView* fviews, const ItemViews& iviews, void* plan
         hipLaunchKernelGGL(k_fovea_classes, dim3(V.ntx32 * V.nty32), dim3(256), 0, s, V, cls);
     }
     hipLaunchKernelGGL(k_fovea_items, dim3(1), dim3(1024), 0, s, iviews, cls, count, items);
+    for (int v = 0; v < vis.n; ++v)
+        hipLaunchKernelGGL(k_vis_tiles, dim3(vis.v[v].ntx * vis.v[v].nty), dim3(256), 0, s, vis.v[v]);
+    hipLaunchKernelGGL(k_vis_sat, dim3(vis.n), dim3(1024), 0, s, vis);
     return launch_status(hipGetLastError());
 }
 

@@ -17,6 +17,7 @@ struct GaussLocal {
     double is[3];  // 1 / s
     double sigma;  // opacity
     bool ok;
+    bool nonfinite;  // a raw parameter (mean, log-scale, quaternion, opacity logit) is NaN or infinite
 };
 
 __device__ inline GaussLocal load_gaussian(const GaussPtrs& g, int i) {
@@ -30,10 +31,14 @@ __device__ inline GaussLocal load_gaussian(const GaussPtrs& g, int i) {
     }
     for (int c = 0; c < 4; ++c) q[c] = double(g.quats[c * n + i]);
     L.sigma = 1.0 / (1.0 + exp(-double(g.opac[i])));
+    bool fin = isfinite(g.opac[i]);
+    for (int c = 0; c < 3; ++c) fin = fin && isfinite(g.means[c * n + i]) && isfinite(g.log_scales[c * n + i]);
+    for (int c = 0; c < 4; ++c) fin = fin && isfinite(g.quats[c * n + i]);
+    L.nonfinite = !fin;
     const double qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     bool ok = qq > 0.0 && isfinite(qq) && isfinite(L.sigma);
     for (int c = 0; c < 3; ++c) ok = ok && isfinite(L.mu[c]) && isfinite(L.s[c]) && L.s[c] > 0.0;
-    L.ok = ok;
+    L.ok = ok && fin;
     // Rotation matrix of the unit quaternion q/|q| (Hamilton convention),
     // written with 2/|q|^2 so that no square root is needed.
     const double k2 = 2.0 / qq;
@@ -56,10 +61,13 @@ struct TileGeo {
     double M[4];       // whitened tangent coords z = M delta / h, |z|^2 = D^2
     double a3x, a3y;   // h = 1 + a3 . delta  (> 0 iff the ray is in front)
     double kappa;      // keep iff D^2_min <= kappa = 2 ln(opacity / alpha_min)
-    double r;          // |mu_c|: the depth when the mean lies in the tile
+    double r;          // |mu_c|: the depth when the mean lies in the tile (per-Gaussian
+                       //   key depths: that key, after K1)
     double n0, nx, ny;         // depth numerator  n0 + nx dx + ny dy
     double w0[3], wx[3], wy[3];  // denominator |w0 + dx wx + dy wy|^2
-    int32_t tx0, ty0, ncx, count;  // candidate tile box origin, width, count
+    int32_t tx0, ty0;    // candidate tile rectangle: origin,
+    uint16_t ncx, ncy;   //   width and height (tiles),
+    int32_t count;       //   and the number of its (visible) tiles
 };
 static_assert(sizeof(TileGeo) == kTileGeoBytes, "TileGeo layout");
 

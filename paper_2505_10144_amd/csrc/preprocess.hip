@@ -58,7 +58,7 @@ __device__ inline void wave_sync_lds() {
 // every store instruction touch 64 different lines).
 __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views, Knobs kn,
                                                     float* __restrict__ proj, TileGeo* __restrict__ tgeo,
-                                                    uint32_t* __restrict__ counts) {
+                                                    uint32_t* __restrict__ counts, int* status) {
     __shared__ float4 stage[4][64 * 8];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -66,6 +66,9 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
     if (wave_i0 >= g.n) return;  // whole wave past the end
     const bool inb = i < g.n;
     const GaussLocal G = load_gaussian(g, inb ? i : wave_i0);
+    // A Gaussian with a NaN or infinite parameter is culled from every view
+    // and reported (once per wave).
+    if (__ballot(inb && G.nonfinite) != 0ull && lane == 0) set_status(status, VRS_ERR_NONFINITE);
     for (int v = 0; v < views.n; ++v) {
         const GeoView& V = views.v[v];
         const size_t slot = size_t(v) * size_t(g.n) + size_t(i);
@@ -80,9 +83,17 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
             TileGeo& t = geo.tg;
             t.tx0 = tx0;
             t.ty0 = ty0;
-            t.ncx = ncx;
-            t.count = ncx * ncy;
-            counts[slot] = uint32_t(ncx * ncy);
+            t.ncx = uint16_t(ncx);
+            t.ncy = uint16_t(ncy);
+            // With visibility culling, only the visible tiles of the
+            // rectangle: four reads of the summed-area table (Fig. 5b).
+            const int cnt = (V.sat && ncx > 0 && ncy > 0) ? int(sat_count(V.sat, V.ntx, tx0, tx1, ty0, ty1))
+                                                         : ncx * ncy;
+            t.count = cnt;
+            counts[slot] = uint32_t(cnt);
+            // Per-Gaussian key depths (view z, distance) replace the per-tile
+            // depth: r then holds the key of every tile of the Gaussian.
+            if (kn.depth_mode == VRS_DEPTH_VIEW_Z) t.r = geo.muc[2];
             tgeo[slot] = t;
             // Render record (field map in vrs_internal.h); the colour goes to
             // the colour array (k_color).
@@ -120,7 +131,7 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
 // else four) that bound the registers their basis values take.  Culled
 // Gaussian-views get a colour too; no list refers to them.
 template <int kColorViews, int kDeg>
-__global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, float* __restrict__ proj) {
+__global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, float* __restrict__ proj, int* status) {
     // No implicit multiply-add contraction: every rounding is the one the
     // source states (the explicit fmaf calls), so a view's colour is the
     // same bits whichever instantiation and view slot computes it.
@@ -163,13 +174,48 @@ __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, floa
 #pragma unroll
         for (int j = 0; j < kColorViews; ++j) {
             if (v0 + j < views.n) {
+                // A colour made non-finite by NaN or infinite coefficients is
+                // taken as black and reported.
+                const bool fin = isfinite(rgb[j][0]) && isfinite(rgb[j][1]) && isfinite(rgb[j][2]);
+                if (!fin) set_status(status, VRS_ERR_NONFINITE);
                 cols[size_t(v0 + j) * size_t(n) + size_t(i)] =
-                    make_float4(fmaxf(rgb[j][0], 0.f), fmaxf(rgb[j][1], 0.f), fmaxf(rgb[j][2], 0.f), 0.f);
+                    fin ? make_float4(fmaxf(rgb[j][0], 0.f), fmaxf(rgb[j][1], 0.f), fmaxf(rgb[j][2], 0.f), 0.f)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
     }
 }
 
+
+// The k-th candidate tile of a Gaussian: the k-th tile of its rectangle in
+// row-major order, or, when some of the rectangle is invisible, the k-th
+// visible one -- rows are skipped by their visible counts and the column is
+// found by a binary search of the row's counts, all from the summed-area
+// table.
+__device__ inline void kth_tile(const GeoView& V, const TileGeo& tg, int k, int& tx, int& ty) {
+    const int ncx = tg.ncx;
+    if (!V.sat || tg.count == ncx * int(tg.ncy)) {
+        tx = tg.tx0 + k % ncx;
+        ty = tg.ty0 + k / ncx;
+        return;
+    }
+    const int x0 = tg.tx0, x1 = tg.tx0 + ncx - 1;
+    int y = tg.ty0;
+    for (;;) {
+        const int rc = int(sat_count(V.sat, V.ntx, x0, x1, y, y));
+        if (k < rc) break;
+        k -= rc;
+        ++y;
+    }
+    int lo = x0, hi = x1;  // smallest x with more than k visible tiles in [x0, x]
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (int(sat_count(V.sat, V.ntx, x0, mid, y, y)) > k) hi = mid;
+        else lo = mid + 1;
+    }
+    tx = lo;
+    ty = y;
+}
 
 // One wave per block owns 64 consecutive (view, Gaussian) slots and deals
 // their candidates out to its lanes 64 at a time, so every lane tests one
@@ -185,9 +231,12 @@ __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const T
                                                   const uint32_t* __restrict__ offsets,
                                                   const uint32_t* __restrict__ counts, size_t nslots,
                                                   uint32_t* __restrict__ n_inst, uint64_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ gids, size_t capacity) {
+                                                  uint32_t* __restrict__ gids, size_t capacity, int kdepth) {
     __shared__ uint32_t pre[65];
     __shared__ GeoView vw[VRS_MAX_VIEWS];
+    // No candidates, or more than the 32-bit offsets can address (the scan
+    // then reports the overflow and leaves a total of 0): nothing to write.
+    if (n_inst[0] == 0u) return;
     const int lane = threadIdx.x;
     const size_t s0 = size_t(blockIdx.x) * 64;
     const size_t nown = min(size_t(64), nslots - s0);
@@ -225,10 +274,12 @@ __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const T
             const GeoView& V = vw[v];
             const TileGeo tg = tgeo[o];
             const int k = int(j - pre[ow]);
-            const int tx = tg.tx0 + k % tg.ncx, ty = tg.ty0 + k / tg.ncx;
+            int tx, ty;
+            kth_tile(V, tg, k, tx, ty);
             double bx0, by0, bx1, by1, depth;
             tile_box(V, tx, ty, bx0, by0, bx1, by1);
             kept = tile_test(tg, V, bx0, by0, bx1, by1, &depth);
+            if (kdepth != VRS_DEPTH_TILE_MAX) depth = tg.r;
             const uint64_t tile = uint64_t(V.tile_off) + uint64_t(ty) * V.ntx + tx;
             keys[cg] = kept ? ((tile << 32) | uint64_t(ord_f32(float(depth)))) : ~0ull;
             gids[cg] = uint32_t(i);
@@ -266,28 +317,28 @@ __global__ void k_dup_init(uint32_t* n_inst, size_t capacity, int* status) {
 // ---------------------------------------------------------------------------
 
 template <int kColorViews>
-void launch_color(const GaussPtrs& g, const GeoViews& views, float* proj, int blocks, hipStream_t s) {
+void launch_color(const GaussPtrs& g, const GeoViews& views, float* proj, int* status, int blocks, hipStream_t s) {
     switch (g.sh_degree) {
-        case 0: hipLaunchKernelGGL((k_color<kColorViews, 0>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
-        case 1: hipLaunchKernelGGL((k_color<kColorViews, 1>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
-        case 2: hipLaunchKernelGGL((k_color<kColorViews, 2>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
-        default: hipLaunchKernelGGL((k_color<kColorViews, 3>), dim3(blocks), dim3(256), 0, s, g, views, proj); break;
+        case 0: hipLaunchKernelGGL((k_color<kColorViews, 0>), dim3(blocks), dim3(256), 0, s, g, views, proj, status); break;
+        case 1: hipLaunchKernelGGL((k_color<kColorViews, 1>), dim3(blocks), dim3(256), 0, s, g, views, proj, status); break;
+        case 2: hipLaunchKernelGGL((k_color<kColorViews, 2>), dim3(blocks), dim3(256), 0, s, g, views, proj, status); break;
+        default: hipLaunchKernelGGL((k_color<kColorViews, 3>), dim3(blocks), dim3(256), 0, s, g, views, proj, status); break;
     }
 }
 
 int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn, float* proj,
-                      uint32_t* counts, hipStream_t s) {
+                      uint32_t* counts, int* status, hipStream_t s) {
     if (g.n == 0) return VRS_OK;
     const size_t nslots = size_t(g.n) * views.n;
     TileGeo* tgeo = reinterpret_cast<TileGeo*>(reinterpret_cast<char*>(proj) + tgeo_offset_bytes(nslots));
     const int blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, s, g, views, kn, proj, tgeo, counts);
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, s, g, views, kn, proj, tgeo, counts, status);
     // Groups of two views for a stereo pair (no work on padding views),
     // else four.
     if (views.n <= 2)
-        launch_color<2>(g, views, proj, blocks, s);
+        launch_color<2>(g, views, proj, status, blocks, s);
     else
-        launch_color<4>(g, views, proj, blocks, s);
+        launch_color<4>(g, views, proj, status, blocks, s);
     return launch_status(hipGetLastError());
 }
 
@@ -296,11 +347,10 @@ int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn
 int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn, const float* proj,
                      const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
                      uint32_t* n_inst, void* ws, int* status, hipStream_t s, bool count_live) {
-    (void)kn;
     const size_t nslots = size_t(g.n) * size_t(views.n);
     uint32_t* offsets = static_cast<uint32_t*>(ws);
     uint32_t* tmp = offsets + nslots;
-    int rc = launch_exclusive_scan(counts, offsets, nslots, n_inst, tmp, s);
+    int rc = launch_exclusive_scan(counts, offsets, nslots, n_inst, tmp, status, s);
     if (rc != VRS_OK) return rc;
     hipLaunchKernelGGL(k_dup_init, dim3(1), dim3(64), 0, s, n_inst, capacity, status);
     if (nslots == 0 || capacity == 0) return launch_status(hipGetLastError());
@@ -308,7 +358,7 @@ int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn,
         reinterpret_cast<const TileGeo*>(reinterpret_cast<const char*>(proj) + tgeo_offset_bytes(nslots));
     const size_t blocks = (nslots + 63) / 64;
     hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(64), 0, s, views, g.n, tgeo, offsets, counts, nslots,
-                       n_inst, keys, gids, capacity);
+                       n_inst, keys, gids, capacity, kn.depth_mode);
     if (count_live) hipLaunchKernelGGL(k_count_live, dim3(256), dim3(256), 0, s, keys, n_inst, capacity);
     return launch_status(hipGetLastError());
 }

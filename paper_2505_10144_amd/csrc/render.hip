@@ -43,10 +43,15 @@ struct Window {
     float t[W], a[W];
     uint32_t id[W];
 
-    __device__ inline void init() {
+    // A window of w <= W entries: w placeholders at -FLT_MAX, which the
+    // first w insertions emit (blending them is a no-op, alpha 0), and W - w
+    // at +FLT_MAX, which no finite depth displaces, so an insertion emits
+    // the smallest of the w real entries and the new one; the final flush
+    // reaches them last, after every real entry.
+    __device__ inline void init(int w) {
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            t[i] = -FLT_MAX;  // placeholders: blending them is a no-op (alpha 0)
+            t[i] = i < w ? -FLT_MAX : FLT_MAX;
             a[i] = 0.f; id[i] = 0u;
         }
     }
@@ -163,6 +168,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     const int sub = item_sub(item);
     const uint32_t tile = item_tile(item);
     const RenderView& V = views.v[v];
+    if (V.skip) return;  // (waves never wait on each other: the whole wave leaves)
     const int T = V.foveated ? 32 : V.T;
     const int tx = int(tile % uint32_t(V.ntx)), ty = int(tile / uint32_t(V.ntx));
     const int ox = tx * T, oy = ty * T;  // sort-tile origin (pixels)
@@ -195,7 +201,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
     acc.T = 1.f; acc.cr = 0.f; acc.cg = 0.f; acc.cb = 0.f;
     acc.alive = inimg;
     Window<W> win;
-    win.init();
+    win.init(kn.window);
 
     const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + tile];
     const float* vproj = proj + size_t(v) * size_t(n_gauss) * kRec;
@@ -385,16 +391,9 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
         }
         return;
     }
-    if (cls == VRS_CLASS_HYBRID) {
-        // Continuous mask from the angle to the fovea-centre ray.
-        const float d0 = (float(px) + 0.5f - V.cx) / V.f, d1 = (float(py) + 0.5f - V.cy) / V.f;
-        const float cx_ = d1 * V.fdir[2] - V.fdir[1];
-        const float cy_ = V.fdir[0] - d0 * V.fdir[2];
-        const float cz_ = d0 * V.fdir[1] - d1 * V.fdir[0];
-        const float dotp = d0 * V.fdir[0] + d1 * V.fdir[1] + V.fdir[2];
-        const float e = atan2f(sqrtf(cx_ * cx_ + cy_ * cy_ + cz_ * cz_), dotp);
-        float wm = (V.rho * (1.f + V.band) - e) / (V.rho * V.band);
-        wm = fminf(fmaxf(wm, 0.f), 1.f);
+    if (cls == VRS_CLASS_HYBRID && !V.nomix) {
+        // The continuous foveation mask at this pixel.
+        const float wm = fovea_weight(V.mask, px, py);
         // Mean of the aligned 2x2 group over its in-image pixels.
         const float cnt0 = inimg ? 1.f : 0.f;
         float cnt = cnt0 + __shfl_xor(cnt0, 1);
@@ -547,13 +546,6 @@ static void launch_render_w(const float* proj, uint32_t n_gauss, const uint32_t*
                                    stats, s);
 }
 
-bool window_supported(int w) {
-    switch (w) {
-        case 1: case 2: case 3: case 4: case 6: case 8: case 12: case 16: case 24: case 32: return true;
-        default: return false;
-    }
-}
-
 int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, const uint32_t* ranges,
                  const uint32_t* items, uint32_t n_items, uint32_t* counter, int batch, int schedule,
                  const RenderViews& views, const Knobs& kn, int window, unsigned long long* stats, hipStream_t s) {
@@ -567,7 +559,7 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
         launch_render_w<w>(proj, n_gauss, gids, ranges, items, n_items, counter, batch, schedule, views, kn, stats, \
                            s);                                                                                    \
         break;
-    switch (window) {
+    switch (window_network(window)) {
         VRS_W(1) VRS_W(2) VRS_W(3) VRS_W(4) VRS_W(6) VRS_W(8) VRS_W(12) VRS_W(16) VRS_W(24) VRS_W(32)
         default: return VRS_ERR_UNSUPPORTED;
     }

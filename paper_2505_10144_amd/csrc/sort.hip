@@ -59,17 +59,34 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t x, uint32_t* sh, uint32
     return below + v - x;
 }
 
+// Sum of a uint64 over the block (every thread gets it).
+__device__ inline uint64_t block_sum_u64(uint64_t x, uint64_t* sh) {
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) t += sh[k];
+    __syncthreads();
+    return t;
+}
+
 // in and out may alias: every thread reads its items before writing them.
+// A block whose items sum to 2^32 - 1 or more stores that saturated value as
+// its sum, which k_scan_sums reports as an overflow.
 __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const uint32_t* in, uint32_t* out,
                                                              uint32_t* __restrict__ sums, size_t n) {
     __shared__ uint32_t sh[kScanThreads];
+    __shared__ uint64_t sh64[kScanThreads / 64];
     const size_t base = size_t(blockIdx.x) * kScanTile + size_t(threadIdx.x) * kScanItems;
     uint32_t v[kScanItems];
     uint32_t s = 0;
+    uint64_t s64 = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         v[k] = base + k < n ? in[base + k] : 0u;
         s += v[k];
+        s64 += v[k];
     }
     uint32_t tot;
     uint32_t ex = block_exclusive_scan(s, sh, tot);
@@ -78,22 +95,30 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const uint32_t* in,
         if (base + k < n) out[base + k] = ex;
         ex += v[k];
     }
-    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+    const uint64_t t64 = block_sum_u64(s64, sh64);
+    if (threadIdx.x == 0) sums[blockIdx.x] = t64 >= 0xFFFFFFFFull ? 0xFFFFFFFFu : tot;
 }
 
 // Single block: exclusive scan of the block sums in chunks with a carry.
+// The grand total is also summed in 64 bits: if it (or a saturated block
+// sum) reaches 2^32 - 1 the offsets are unrepresentable, so the total is
+// set to 0 (nothing downstream reads an offset) and the overflow reported.
 __global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t* __restrict__ sums, size_t nb,
-                                                            uint32_t* __restrict__ total) {
+                                                            uint32_t* __restrict__ total, int* status) {
     __shared__ uint32_t sh[kScanThreads];
+    __shared__ uint64_t sh64[kScanThreads / 64];
     uint32_t carry = 0;
+    uint64_t carry64 = 0;
     for (size_t c0 = 0; c0 < nb; c0 += kScanTile) {
         const size_t base = c0 + size_t(threadIdx.x) * kScanItems;
         uint32_t v[kScanItems];
         uint32_t s = 0;
+        uint64_t s64 = 0;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             v[k] = base + k < nb ? sums[base + k] : 0u;
             s += v[k];
+            s64 += v[k];
         }
         uint32_t tot;
         uint32_t ex = block_exclusive_scan(s, sh, tot) + carry;
@@ -103,8 +128,13 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t* __restrict
             ex += v[k];
         }
         carry += tot;
+        carry64 += block_sum_u64(s64, sh64);
     }
-    if (threadIdx.x == 0 && total) *total = carry;
+    if (threadIdx.x == 0) {
+        const bool over = carry64 >= 0xFFFFFFFFull;
+        if (over) set_status(status, VRS_ERR_UNSUPPORTED);
+        if (total) *total = over ? 0u : carry;
+    }
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_add(uint32_t* __restrict__ out,
@@ -122,14 +152,14 @@ __global__ void k_store_zero(uint32_t* p) {
 size_t scan_tmp_words(size_t n) { return (n + kScanTile - 1) / kScanTile + 64; }
 
 int launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* total, uint32_t* tmp,
-                          hipStream_t s) {
+                          int* status, hipStream_t s) {
     if (n == 0) {
         if (total) hipLaunchKernelGGL(k_store_zero, dim3(1), dim3(64), 0, s, total);
         return launch_status(hipGetLastError());
     }
     const size_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanThreads), 0, s, in, out, tmp, n);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, total);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, total, status);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, s, out, tmp, n);
     return launch_status(hipGetLastError());
 }

@@ -70,7 +70,11 @@ def upload(scene, device="cuda") -> Gaussians:
 
 class Renderer:
     def __init__(self, cams: Sequence, foveas, params, n: int, device="cuda",
-                 capacity: Optional[int] = None, stream=None):
+                 capacity: Optional[int] = None, stream=None, masks=None):
+        """``masks``: optional per-view headset visibility masks (uint8
+        arrays or tensors [H][W], nonzero = visible, or None) for
+        visibility culling; they are copied to the device and consumed by
+        the plan."""
         if not isinstance(foveas, (list, tuple)):
             foveas = [foveas] * len(cams)
         if len(cams) != len(foveas):
@@ -102,7 +106,18 @@ class Renderer:
         if capacity is not None:
             self._alloc_instances(int(capacity))
         n_items = ctypes.c_uint32(0)
-        L.call("vrs_fovea_plan", self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params),
+        mask_t = [None] * self.V
+        if masks is not None:
+            for v, m in enumerate(masks):
+                if m is None:
+                    continue
+                m = torch.as_tensor(np.asarray(m.cpu() if torch.is_tensor(m) else m, dtype=np.uint8))
+                if tuple(m.shape) != (self.cams[v].height, self.cams[v].width):
+                    raise ValueError("a visibility mask is [height][width]")
+                mask_t[v] = m.contiguous().to(dev)
+        self.masks = mask_t
+        mask_ptrs = (ctypes.c_void_p * self.V)(*[(m.data_ptr() if m is not None else 0) for m in mask_t])
+        L.call("vrs_fovea_plan", self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), mask_ptrs,
                _ptr(self.plan), ctypes.c_size_t(self.plan.numel()), ctypes.byref(n_items),
                _stream(self.stream))
         self.n_items = int(n_items.value)
@@ -132,7 +147,7 @@ class Renderer:
         self.preprocess(g)
         self.status.zero_()
         L.call("vrs_duplicate", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
-               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
+               ctypes.byref(self.c_params), _ptr(self.plan), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
                _ptr(self.gids), ctypes.c_size_t(0), _ptr(self.n_inst), _ptr(self.sort_ws),
                ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status), _stream(self.stream))
         need = int(self.n_inst[0].item())
@@ -144,12 +159,12 @@ class Renderer:
     # -- stages -------------------------------------------------------------------
     def preprocess(self, g: Gaussians):
         L.call("vrs_preprocess", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
-               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.status),
-               _stream(self.stream))
+               ctypes.byref(self.c_params), _ptr(self.plan), _ptr(self.proj), _ptr(self.counts),
+               _ptr(self.status), _stream(self.stream))
 
     def duplicate(self, g: Gaussians):
         L.call("vrs_duplicate", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
-               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
+               ctypes.byref(self.c_params), _ptr(self.plan), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
                _ptr(self.gids), ctypes.c_size_t(self.capacity), _ptr(self.n_inst), _ptr(self.sort_ws),
                ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status), _stream(self.stream))
 
@@ -161,7 +176,7 @@ class Renderer:
 
     def sort(self, g: Gaussians):
         L.call("vrs_sort", ctypes.byref(g.struct()), self.c_cams, self.c_fovs, self.V,
-               ctypes.byref(self.c_params), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
+               ctypes.byref(self.c_params), _ptr(self.plan), _ptr(self.proj), _ptr(self.counts), _ptr(self.keys),
                _ptr(self.gids),
                ctypes.c_size_t(self.capacity), _ptr(self.n_inst), _ptr(self.ranges),
                _ptr(self.sort_ws), ctypes.c_size_t(self.sort_ws.numel()), _ptr(self.status),
@@ -211,7 +226,8 @@ class Renderer:
         """Gradients of sum_v <grad_images[v], images[v]> with respect to the
         Gaussian parameters, for the forward pass whose state (records,
         sorted instances, ranges) this renderer currently holds.  ``images``
-        defaults to the renderer's own output buffers.  Plain views only."""
+        defaults to the renderer's own output buffers (plain views; a
+        foveated view's backward re-renders its samples instead)."""
         if g.n != self.n:
             raise ValueError("Gaussian count differs from the renderer's")
         images = list(images) if images is not None else self.images
@@ -222,7 +238,8 @@ class Renderer:
             if tuple(gi.shape) != (4, c.height, c.width) or not gi.is_cuda:
                 raise ValueError("gradients must be (4, H, W) CUDA tensors")
         imgs = [im.contiguous() for im in images]
-        need = int(L.load().vrs_backward_workspace_size(self.n, self.V))
+        need = int(L.load().vrs_backward_workspace_size(self.n, self.c_cams, self.c_fovs, self.V,
+                                                        ctypes.byref(self.c_params)))
         if getattr(self, "bwd_ws", None) is None or self.bwd_ws.numel() < max(need, 256):
             self.bwd_ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         dev = self.device
@@ -238,7 +255,8 @@ class Renderer:
         img_ptrs = (ctypes.c_void_p * self.V)(*[im.data_ptr() for im in imgs])
         grad_ptrs = (ctypes.c_void_p * self.V)(*[gi.data_ptr() for gi in grads])
         L.call("vrs_render_backward", ctypes.byref(g.struct()), _ptr(self.proj), _ptr(self.gids),
-               _ptr(self.ranges), self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), img_ptrs,
+               _ptr(self.ranges), self.c_cams, self.c_fovs, self.V, ctypes.byref(self.c_params), _ptr(self.plan),
+               ctypes.c_uint32(self.n_items), img_ptrs,
                grad_ptrs, ctypes.byref(gs), _ptr(self.bwd_ws), ctypes.c_size_t(self.bwd_ws.numel()),
                _ptr(self.status), _stream(self.stream))
         # Keep the inputs alive until the kernels that read them are done.
@@ -262,6 +280,21 @@ class Renderer:
         off = L.PLAN_ITEMS_OFFSET + 4 * self.items_max
         return self.plan[off:].cpu().numpy()
 
+    def pre_images(self) -> List[torch.Tensor]:
+        """Per view, the blend's output before the periphery compose: for a
+        foveated view the pre-compose image in the render workspace (LOW
+        groups written to their 2x2 pixels, HYBRID pixels already mixed), for
+        a plain view the output image itself."""
+        out, off = [], 0
+        for c, f, im in zip(self.cams, self.foveas, self.images):
+            if f.enabled:
+                n = 4 * c.width * c.height
+                out.append(self.render_ws[4 * off:4 * (off + n)].view(torch.float32).view(4, c.height, c.width))
+                off += n
+            else:
+                out.append(im)
+        return out
+
     def records(self) -> torch.Tensor:
         return self.proj[: self.V * self.n * L.VRS_RECORD_FLOATS * 4].view(torch.float32).view(
             self.V, self.n, L.VRS_RECORD_FLOATS)
@@ -271,3 +304,95 @@ class Renderer:
         after the render and tile-test records in `proj`."""
         off = self.V * self.n * (L.VRS_RECORD_FLOATS * 4 + L.TILEGEO_BYTES)
         return self.proj[off: off + self.V * self.n * 16].view(torch.float32).view(self.V, self.n, 4)
+
+
+class _Cam:
+    """A camera description read back from the library (the attributes
+    ``_lib.make_camera`` reads)."""
+
+    def __init__(self, c: L.vrs_camera):
+        self.world_to_cam = np.array(list(c.world_to_cam), np.float32).reshape(3, 4)
+        self.fov_x_deg = float(c.fov_x_deg)
+        self.cx = float(c.cx)
+        self.cy = float(c.cy)
+        self.width = int(c.width)
+        self.height = int(c.height)
+
+
+class TwoPassRenderer:
+    """The two-pass foveated baseline (App. A) over the same library: a
+    centre pass at full resolution through the tight frustum of the centre
+    region, a periphery pass at half resolution (both plain renders with
+    16x16 tiles, all views of a pass in one call sequence), then
+    vrs_two_pass_compose blends them into the output images."""
+
+    def __init__(self, cams: Sequence, foveas, params, n: int, device="cuda", stream=None):
+        if not isinstance(foveas, (list, tuple)):
+            foveas = [foveas] * len(cams)
+        self.cams, self.foveas, self.params = list(cams), list(foveas), params
+        self.V = len(self.cams)
+        self.stream = stream
+        self.c_cams = L.camera_array(self.cams)
+        self.c_fovs = L.fovea_array(self.foveas)
+        # The single-pass plan of these views gives the centre region.
+        plan_r = Renderer(self.cams, self.foveas, params, n, device=device, stream=stream)
+        ccams = (L.vrs_camera * self.V)()
+        lcams = (L.vrs_camera * self.V)()
+        boxes = (ctypes.c_int32 * (4 * self.V))()
+        L.call("vrs_two_pass_views", self.c_cams, self.c_fovs, self.V, ctypes.byref(plan_r.c_params),
+               _ptr(plan_r.plan), ccams, boxes, lcams, _stream(stream))
+        del plan_r
+        self.boxes = boxes
+        self.box_list = [tuple(boxes[4 * v:4 * v + 4]) for v in range(self.V)]
+        self.centre_views = [v for v in range(self.V) if self.box_list[v][2] > self.box_list[v][0]]
+        off = [synth_fovea_off() for _ in range(self.V)]
+        p1 = params.replace(tile=16)
+        p2 = params.replace(tile=16, dilation=float(np.float32(params.dilation) * np.float32(0.25)))
+        self.centre_cams = [_Cam(ccams[v]) for v in self.centre_views]
+        self.low_cams = [_Cam(lcams[v]) for v in range(self.V)]
+        self.centre = (Renderer(self.centre_cams, off[:len(self.centre_cams)], p1, n, device=device, stream=stream)
+                       if self.centre_views else None)
+        self.low = Renderer(self.low_cams, off, p2, n, device=device, stream=stream)
+        self.images = [torch.empty((4, c.height, c.width), dtype=torch.float32, device=device) for c in self.cams]
+        self._out_ptrs = (ctypes.c_void_p * self.V)(*[im.data_ptr() for im in self.images])
+
+    def ensure_capacity(self, g: Gaussians):
+        if self.centre is not None:
+            self.centre.ensure_capacity(g)
+        self.low.ensure_capacity(g)
+
+    def render(self, g: Gaussians) -> List[torch.Tensor]:
+        """Both passes, then the blend."""
+        cimgs = self.centre.render(g) if self.centre is not None else []
+        limgs = self.low.render(g)
+        self.compose(cimgs, limgs)
+        return self.images
+
+    def compose(self, cimgs=None, limgs=None):
+        cimgs = self.centre.images if cimgs is None and self.centre is not None else (cimgs or [])
+        limgs = self.low.images if limgs is None else limgs
+        cptr = [0] * self.V
+        for k, v in enumerate(self.centre_views):
+            cptr[v] = cimgs[k].data_ptr()
+        c_arr = (ctypes.c_void_p * self.V)(*cptr)
+        l_arr = (ctypes.c_void_p * self.V)(*[im.data_ptr() for im in limgs])
+        L.call("vrs_two_pass_compose", self.c_cams, self.c_fovs, self.V, self.boxes, c_arr, l_arr,
+               self._out_ptrs, _stream(self.stream))
+
+    def check(self):
+        n = self.low.check()
+        if self.centre is not None:
+            n += self.centre.check()
+        return n
+
+
+def synth_fovea_off():
+    """A disabled fovea (the attributes ``_lib.make_fovea`` reads)."""
+    class _F:
+        enabled = False
+        center_px = (0.0, 0.0)
+        radius_deg = 0.0
+        band_frac = 0.0
+        shape = 0
+        half_px = (0.0, 0.0)
+    return _F()

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "vrs.h")
 def header_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(vrs_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(vrs_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -69,7 +69,8 @@ def test_workspace_size_plain_and_tile32():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(tile=8), dict(window=0), dict(window=33), dict(alpha_min=0.0), dict(alpha_min=1.0),
+    dict(tile=8), dict(window=-1), dict(window=33), dict(alpha_min=0.0), dict(alpha_min=1.0),
+    dict(depth=3), dict(depth=-1),
     dict(schedule=2), dict(schedule=-1),
     dict(t_min=0.0), dict(z_near=0.0), dict(dilation=-1.0), dict(alpha_max=0.001),
 ])
@@ -82,10 +83,11 @@ def test_invalid_params_rejected(bad):
     assert rc == L.VRS_ERR_INVALID_ARG
 
 
-def test_unsupported_window_and_batch():
+def test_every_window_accepted_and_unsupported_batch():
     cam = synth.camera_translate((0, 0, -3), 90, 64, 64)
-    rc, _ = _sizes(10, [cam], [synth.fovea_off()], synth.default_params(window=5))
-    assert rc == L.VRS_ERR_UNSUPPORTED
+    for w in range(0, 33):
+        rc, _ = _sizes(10, [cam], [synth.fovea_off()], synth.default_params(window=w))
+        assert rc == L.VRS_OK, w
     rc, _ = _sizes(10, [cam], [synth.fovea_off()], synth.default_params(blend_batch=96))
     assert rc == L.VRS_ERR_UNSUPPORTED
 
@@ -112,12 +114,12 @@ def test_entry_points_validate_before_device_work():
     g.n = 5
     g.sh_degree = 4  # invalid
     null = ctypes.c_void_p(0)
-    assert lib.vrs_preprocess(ctypes.byref(g), cam, fov, 1, ctypes.byref(p), null, null, null, null) == L.VRS_ERR_INVALID_ARG
+    assert lib.vrs_preprocess(ctypes.byref(g), cam, fov, 1, ctypes.byref(p), null, null, null, null, null) == L.VRS_ERR_INVALID_ARG
     g.sh_degree = 3  # valid degree but NULL parameter pointers
-    assert lib.vrs_preprocess(ctypes.byref(g), cam, fov, 1, ctypes.byref(p), null, null, null, null) == L.VRS_ERR_INVALID_ARG
+    assert lib.vrs_preprocess(ctypes.byref(g), cam, fov, 1, ctypes.byref(p), null, null, null, null, null) == L.VRS_ERR_INVALID_ARG
     assert lib.vrs_sort_pairs(null, null, null, 10, 40, null, 0, null, null) == L.VRS_ERR_INVALID_ARG
     assert lib.vrs_sort_pairs(null, null, null, 10, 65, null, 0, null, null) == L.VRS_ERR_INVALID_ARG
-    assert lib.vrs_fovea_plan(cam, fov, 1, ctypes.byref(p), null, 0, None, null) == L.VRS_ERR_INVALID_ARG
+    assert lib.vrs_fovea_plan(cam, fov, 1, ctypes.byref(p), None, null, 0, None, null) == L.VRS_ERR_INVALID_ARG
     imgs = (ctypes.c_void_p * 1)(0)
     assert lib.vrs_render_foveated(null, -1, null, null, cam, fov, 1, ctypes.byref(p), null, 0, imgs, null, 0,
                                    null, null) == L.VRS_ERR_INVALID_ARG
