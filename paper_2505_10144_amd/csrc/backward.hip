@@ -88,13 +88,14 @@ struct BWindow {
         ek = c[0] ? k[0] : xk;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            t[i] = c[i] ? xt : t[i];
             a[i] = c[i] ? xa : a[i];
             k[i] = c[i] ? xk : k[i];
             if (i + 1 < W) {
-                t[i] = c[i + 1] ? t[i + 1] : t[i];
+                t[i] = __builtin_amdgcn_fmed3f(t[i], xt, t[i + 1]);  // as in k_render
                 a[i] = c[i + 1] ? a[i + 1] : a[i];
                 k[i] = c[i + 1] ? k[i + 1] : k[i];
+            } else {
+                t[i] = c[i] ? xt : t[i];
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -459,8 +460,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             const bool pass = alive && (h > 0.f) && (q <= f2.y * h2);
             if (__ballot(pass) != 0ull) {  // wave-uniform
                 const float4 f3 = ring[3][base + j], f4 = ring[4][base + j], f5 = ring[5][base + j];
-                const float xa =
-                    pass ? fminf(amax, __builtin_amdgcn_exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2))) : 0.f;
+                const float xa = pass ? splat_alpha(f2.x, q, h2, amax) : 0.f;
                 const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
                 const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
                 const float w1 = fmaf(f4.y, dx, fmaf(f5.x, dy, f3.z));

@@ -55,7 +55,13 @@ __device__ inline void wave_sync_lds() {
 
 // The render records of a wave's 64 consecutive Gaussians are staged in LDS
 // and written out as contiguous 1 KB pieces (a record per lane would make
-// every store instruction touch 64 different lines).
+// every store instruction touch 64 different lines).  In LDS, field f of
+// record r sits at r * 8 + (f ^ (r & 7)), so the 64 lanes writing one field
+// of their records spread over all banks (a record-major layout puts every
+// lane of such a store in the same four banks), and the write-out still
+// reads each record's eight fields as one contiguous 128-byte run.
+__device__ inline int stage_slot(int r, int f) { return r * 8 + (f ^ (r & 7)); }
+
 __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views, Knobs kn,
                                                     float* __restrict__ proj, TileGeo* __restrict__ tgeo,
                                                     uint32_t* __restrict__ counts, int* status) {
@@ -99,15 +105,17 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
             // the colour array (k_color).
             const double xi = floor(t.x0), yi = floor(t.y0);
             const float zs = float(sqrt(0.5 / M_LN2));  // |z|^2 = (log2 e / 2) D^2
-            float4* st = &stage[w][lane * 8];
-            st[0] = make_float4(float(xi), float(yi), float(t.x0 - xi), float(t.y0 - yi));
-            st[1] = make_float4(float(t.M[0]) * zs, float(t.M[1]) * zs, float(t.M[2]) * zs, float(t.M[3]) * zs);
-            st[2] = make_float4(float(t.a3x), float(t.a3y), float(geo.l2s), float(t.kappa * (0.5 * M_LOG2E)));
-            st[3] = make_float4(float(t.n0), float(t.nx), float(t.ny), float(G.sigma));
-            st[4] = make_float4(float(t.w0[0]), float(t.w0[1]), float(t.w0[2]), float(t.wx[0]));
-            st[5] = make_float4(float(t.wx[1]), float(t.wx[2]), float(t.wy[0]), float(t.wy[1]));
-            st[6] = make_float4(float(t.wy[2]), 0.f, 0.f, 0.f);
-            st[7] = make_float4(bbox[0], bbox[1], bbox[2], bbox[3]);
+            float4* st = stage[w];
+            st[stage_slot(lane, 0)] = make_float4(float(xi), float(yi), float(t.x0 - xi), float(t.y0 - yi));
+            st[stage_slot(lane, 1)] =
+                make_float4(float(t.M[0]) * zs, float(t.M[1]) * zs, float(t.M[2]) * zs, float(t.M[3]) * zs);
+            st[stage_slot(lane, 2)] =
+                make_float4(float(t.a3x), float(t.a3y), float(geo.l2s), float(t.kappa * (0.5 * M_LOG2E)));
+            st[stage_slot(lane, 3)] = make_float4(float(t.n0), float(t.nx), float(t.ny), float(G.sigma));
+            st[stage_slot(lane, 4)] = make_float4(float(t.w0[0]), float(t.w0[1]), float(t.w0[2]), float(t.wx[0]));
+            st[stage_slot(lane, 5)] = make_float4(float(t.wx[1]), float(t.wx[2]), float(t.wy[0]), float(t.wy[1]));
+            st[stage_slot(lane, 6)] = make_float4(float(t.wy[2]), 0.f, 0.f, 0.f);
+            st[stage_slot(lane, 7)] = make_float4(bbox[0], bbox[1], bbox[2], bbox[3]);
         }
         const uint64_t okm = __ballot(ok);
         wave_sync_lds();
@@ -116,7 +124,7 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int q = c * 64 + lane;
-            if ((okm >> (q >> 3)) & 1ull) dst[q] = stage[w][q];
+            if ((okm >> (q >> 3)) & 1ull) dst[q] = stage[w][stage_slot(q >> 3, q & 7)];
         }
         wave_sync_lds();
     }

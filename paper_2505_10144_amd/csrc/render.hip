@@ -60,8 +60,10 @@ struct Window {
     // With c[i] = (t[i] <= x.t) (a prefix of the sorted window), the result
     // is: emitted = c[0] ? slot 0 : x, and slot i becomes slot i+1 if
     // c[i+1], else x if c[i], else stays -- so a window entry wins ties (it
-    // arrived earlier).  Slots are rewritten in ascending order, each from
-    // itself and its not-yet-rewritten neighbour, so the update is in place.
+    // arrived earlier).  For the depths that is the median of t[i], x.t and
+    // t[i+1] (one instruction); alpha and index follow the masks.  Slots are
+    // rewritten in ascending order, each from itself and its not-yet-
+    // rewritten neighbour, so the update is in place.
     // Pushing an entry with t = -inf and alpha = 0 leaves the window
     // unchanged and returns that entry, whose blend is a no-op: lanes with
     // nothing to insert run the same instructions as the others.
@@ -75,13 +77,14 @@ struct Window {
         e.id = c[0] ? id[0] : x.id;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            t[i] = c[i] ? x.t : t[i];
             a[i] = c[i] ? x.a : a[i];
             id[i] = c[i] ? x.id : id[i];
             if (i + 1 < W) {
-                t[i] = c[i + 1] ? t[i + 1] : t[i];
+                t[i] = __builtin_amdgcn_fmed3f(t[i], x.t, t[i + 1]);
                 a[i] = c[i + 1] ? a[i + 1] : a[i];
                 id[i] = c[i + 1] ? id[i + 1] : id[i];
+            } else {
+                t[i] = c[i] ? x.t : t[i];
             }
             // Keep each slot's update together so that it can be done in
             // the slot's own registers (no rotation copies at the loop edge).
@@ -115,13 +118,6 @@ struct Accum {
         cr = fmaf(w, r, cr);
         cg = fmaf(w, g, cg);
         cb = fmaf(w, b, cb);
-    }
-    // add() for a colour that need not have been loaded when w = 0.
-    __device__ inline void add_if(float w, float r, float g, float b) {
-        const bool z = w == 0.f;
-        cr = z ? cr : fmaf(w, r, cr);
-        cg = z ? cg : fmaf(w, g, cg);
-        cb = z ? cb : fmaf(w, b, cb);
     }
 };
 
@@ -244,11 +240,12 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
         const Slot e = win.push(x);
         const float w = acc.weight(e.a, tmin);
         // Add the previous emission, whose colour load was issued one step
-        // earlier (a zero weight adds nothing), then issue this one's.  The
-        // load is unconditional so that it lands straight in the registers
-        // the next step reads: e.id is a list entry's Gaussian or the
-        // placeholder 0, and the wave has list entries, so the record exists.
-        acc.add_if(pw, pc.x, pc.y, pc.z);
+        // earlier (a zero weight adds nothing: colours are finite), then
+        // issue this one's.  The load is unconditional so that it lands
+        // straight in the registers the next step reads: e.id is a list
+        // entry's Gaussian or the placeholder 0, and the wave has list
+        // entries, so the record exists.
+        acc.add(pw, pc.x, pc.y, pc.z);
         pw = w;
         pc = gauss_colour(vcol, e.id);
     };
@@ -310,10 +307,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
             }
             if (pass) {
                 const float4 f3 = st[j][3], f4 = st[j][4], f5 = st[j][5];
-                // The hardware exp2 (no denormal range handling): a passing
-                // pair's exponent is at least log2(alpha_min), far inside the
-                // normal range, where it equals exp2f.
-                const float a = fminf(amax, __builtin_amdgcn_exp2f(f2.x - q * __builtin_amdgcn_rcpf(h2)));
+                const float a = splat_alpha(f2.x, q, h2, amax);
                 const float num = fmaf(f2.w, dx, fmaf(f3.x, dy, f2.z));
                 const float w0 = fmaf(f4.x, dx, fmaf(f4.w, dy, f3.y));
                 const float w1 = fmaf(f4.y, dx, fmaf(f5.x, dy, f3.z));
@@ -345,7 +339,7 @@ __device__ inline void render_unit(uint32_t item, int wv, float4 (*st)[kStage], 
         if (__ballot(i < cnt) == 0ull) break;  // wave-uniform
         drain_step(i);
     }
-    acc.add_if(pw, pc.x, pc.y, pc.z);
+    acc.add(pw, pc.x, pc.y, pc.z);
     // Flush the window in ascending depth order: weights first (they chain
     // through T), then the colours, four loads in flight at a time (which
     // keeps the register peak down).

@@ -119,6 +119,16 @@ __host__ __device__ inline int window_network(int w) {
     return w <= 1 ? 1 : w <= 4 ? w : w <= 6 ? 6 : w <= 8 ? 8 : w <= 12 ? 12 : w <= 16 ? 16 : w <= 24 ? 24 : 32;
 }
 
+// Alpha of a (sample, entry) pair that passed the alpha_min test: opacity
+// 2^(-q / h^2) with q = |M delta|^2 and h = 1 + a3 . delta, clamped to
+// alpha_max.  One definition for the forward blend and the backward replay,
+// so that both take the same roundings.  The hardware exp2 has no denormal
+// range handling; a passing pair's exponent is at least log2(alpha_min),
+// far inside the normal range, where it equals exp2f.
+__device__ inline float splat_alpha(float l2s, float q, float h2, float amax) {
+    return fminf(amax, __builtin_amdgcn_exp2f(fmaf(-q, __builtin_amdgcn_rcpf(h2), l2s)));
+}
+
 // Per-view data for the render and compose kernels.
 // The continuous foveation mask in FP32 (HYBRID blending, two-pass blend).
 struct FovMaskF {
