@@ -156,7 +156,7 @@ typedef struct {
 typedef struct {
     size_t proj_bytes;       /* per view and Gaussian: a 128-byte FP32 render record
                                 ([n_views][n][32] floats); after all of them a
-                                192-byte FP64 tile-test record each; after those a
+                                16-byte candidate tile rectangle each; after those a
                                 float4 colour (r, g, b, 0) each                      */
     size_t counts_bytes;     /* uint32 counts[n_views][n]                         */
     uint32_t tiles_total;    /* sum over views of sort-grid tiles (ranges rows)    */
@@ -200,10 +200,10 @@ int vrs_fovea_plan(const vrs_camera* cams, const vrs_fovea* foveas, int32_t n_vi
  * and Sec. 4.2, SH colour; one thread per Gaussian covering every view).
  * Writes into `proj` (proj_bytes, 16-byte aligned) each Gaussian's FP32
  * render record per view -- rows [n_views][n][VRS_RECORD_FLOATS] -- its
- * FP64 tile-test record and its colour, and into counts[n_views][n] the number of candidate
+ * candidate tile rectangle and its colour, and into counts[n_views][n] the number of candidate
  * tiles: the tiles meeting the image of the cone of directions in which the
  * splat can reach alpha_min (a conservative bound; the exact tile test of
- * Eq. 4 runs in vrs_duplicate).  With a plan (from vrs_fovea_plan with the
+ * Eq. 4 runs in vrs_duplicate, which derives the FP64 set-up again from `g`).  With a plan (from vrs_fovea_plan with the
  * same cameras, foveas and params; may be null) only the visible tiles of
  * that rectangle are counted, exactly, from the plan's summed-area table at
  * the rectangle's corners (Sec. 4.3, Fig. 5b).  Culled Gaussians (camera z <= z_near,
@@ -233,8 +233,10 @@ int vrs_preprocess(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fov
  * first `capacity` slots are written.  If there are 2^32 - 1 candidates or
  * more (beyond the 32-bit instance offsets), *status_dev =
  * VRS_ERR_UNSUPPORTED, n_inst_dev[0] = n_inst_dev[1] = 0 and nothing is
- * written.  `proj`/`counts` come from vrs_preprocess; `ws` must hold
- * sort_ws_bytes. */
+ * written.  `proj`/`counts` come from vrs_preprocess with the same `g`,
+ * cameras and params (the FP64 tile-test set-up of each counted Gaussian
+ * is derived again here from `g`, by the code vrs_preprocess ran); `ws`
+ * must hold sort_ws_bytes. */
 int vrs_duplicate(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* foveas,
                   int32_t n_views, const vrs_params* p, const void* plan, const void* proj,
                   const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
@@ -261,7 +263,7 @@ size_t vrs_sort_pairs_workspace_size(size_t capacity);
  * fixed device array inside the library instead of caller memory, so the
  * call allocates nothing.  Each GPU the library runs on holds its own array
  * of vrs_sort_pairs_workspace_size(VRS_SORT_NOALLOC_MAX_PAIRS) bytes (about
- * 33 MiB) until the process ends.  capacity > VRS_SORT_NOALLOC_MAX_PAIRS
+ * 30 MiB) until the process ends.  capacity > VRS_SORT_NOALLOC_MAX_PAIRS
  * returns VRS_ERR_SCRATCH with nothing enqueued.  Every call on one GPU uses
  * that GPU's one array: calls that may overlap on the same GPU (other
  * streams, other host threads) race and must be serialised by the caller.

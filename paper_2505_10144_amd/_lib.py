@@ -19,7 +19,7 @@ VRS_SORT_NOALLOC_MAX_PAIRS = 2097152
 VRS_MAX_VIEWS = 32
 VRS_MAX_WINDOW = 32
 VRS_RECORD_FLOATS = 32
-TILEGEO_BYTES = 192  # FP64 tile-test record per (view, Gaussian), after the render records
+TILERECT_BYTES = 16  # candidate tile rectangle per (view, Gaussian), after the render records
 VRS_CLASS_LOW, VRS_CLASS_HIGH, VRS_CLASS_HYBRID, VRS_CLASS_PLAIN = 0, 1, 2, 3
 VRS_SCHEDULE_ONESHOT, VRS_SCHEDULE_PERSISTENT = 0, 1
 PLAN_ITEMS_OFFSET = 256

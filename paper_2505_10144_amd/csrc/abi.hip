@@ -20,7 +20,7 @@ int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*,
 
 // Bytes per Gaussian and view in `proj`: the FP32 render record plus the FP64
 // tile-test record (TileGeo, 192 bytes) that instantiation reads.
-constexpr size_t kProjBytesPerSlot = kRec * sizeof(float) + kTileGeoBytes + 4 * sizeof(float);
+constexpr size_t kProjBytesPerSlot = kRec * sizeof(float) + kTileRectBytes + 4 * sizeof(float);
 size_t dup_ws_bytes(size_t nslots) { return (nslots + scan_tmp_words(nslots) + 64) * sizeof(uint32_t); }
 int launch_tile_ranges(const uint64_t*, const uint32_t*, size_t, uint32_t, uint32_t*, hipStream_t);
 int launch_blend(const float*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*, int,

@@ -55,7 +55,10 @@ __device__ inline GaussLocal load_gaussian(const GaussPtrs& g, int i) {
     return L;
 }
 
-// What K3 needs of one Gaussian in one view, stored by K1 (192 bytes).
+// The FP64 tile-test set-up of one Gaussian in one view.  K1 derives it for
+// the render record and the candidate rectangle; K3 derives it again from
+// the Gaussian's parameters (the same code on the same inputs, so the same
+// values) rather than reading 176 bytes per Gaussian-view back from memory.
 struct TileGeo {
     double x0, y0;     // image point of the mean (pixels)
     double M[4];       // whitened tangent coords z = M delta / h, |z|^2 = D^2
@@ -65,11 +68,15 @@ struct TileGeo {
                        //   key depths: that key, after K1)
     double n0, nx, ny;         // depth numerator  n0 + nx dx + ny dy
     double w0[3], wx[3], wy[3];  // denominator |w0 + dx wx + dy wy|^2
+};
+
+// A Gaussian's candidate tiles in one view, stored by K1 for K3.
+struct TileRect {
     int32_t tx0, ty0;    // candidate tile rectangle: origin,
     uint16_t ncx, ncy;   //   width and height (tiles),
     int32_t count;       //   and the number of its (visible) tiles
 };
-static_assert(sizeof(TileGeo) == kTileGeoBytes, "TileGeo layout");
+static_assert(sizeof(TileRect) == kTileRectBytes, "TileRect layout");
 
 // Everything K1 derives for one Gaussian in one view.
 struct Geo {

@@ -6,7 +6,7 @@
 //
 // The array is a file-scope __device__ variable: every GPU the library runs
 // on holds its own copy (sort_ws_layout_bytes(VRS_SORT_NOALLOC_MAX_PAIRS),
-// about 33 MiB) from module load until the process ends.  Its host-side name
+// about 30 MiB) from module load until the process ends.  Its host-side name
 // is not a device address, so the device address is taken once per device
 // with hipGetSymbolAddress (with that device current) and only that address
 // is handed to kernels.

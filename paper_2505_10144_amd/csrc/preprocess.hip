@@ -63,7 +63,7 @@ __device__ inline void wave_sync_lds() {
 __device__ inline int stage_slot(int r, int f) { return r * 8 + (f ^ (r & 7)); }
 
 __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views, Knobs kn,
-                                                    float* __restrict__ proj, TileGeo* __restrict__ tgeo,
+                                                    float* __restrict__ proj, TileRect* __restrict__ rects,
                                                     uint32_t* __restrict__ counts, int* status) {
     __shared__ float4 stage[4][64 * 8];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -86,21 +86,19 @@ __global__ void __launch_bounds__(256) k_preprocess(GaussPtrs g, GeoViews views,
             float bbox[4];
             cone_tiles(geo, V, tx0, tx1, ty0, ty1, bbox);
             const int ncx = max(tx1 - tx0 + 1, 0), ncy = max(ty1 - ty0 + 1, 0);
-            TileGeo& t = geo.tg;
-            t.tx0 = tx0;
-            t.ty0 = ty0;
-            t.ncx = uint16_t(ncx);
-            t.ncy = uint16_t(ncy);
+            const TileGeo& t = geo.tg;
+            TileRect rc;
+            rc.tx0 = tx0;
+            rc.ty0 = ty0;
+            rc.ncx = uint16_t(ncx);
+            rc.ncy = uint16_t(ncy);
             // With visibility culling, only the visible tiles of the
             // rectangle: four reads of the summed-area table (Fig. 5b).
             const int cnt = (V.sat && ncx > 0 && ncy > 0) ? int(sat_count(V.sat, V.ntx, tx0, tx1, ty0, ty1))
                                                          : ncx * ncy;
-            t.count = cnt;
+            rc.count = cnt;
             counts[slot] = uint32_t(cnt);
-            // Per-Gaussian key depths (view z, distance) replace the per-tile
-            // depth: r then holds the key of every tile of the Gaussian.
-            if (kn.depth_mode == VRS_DEPTH_VIEW_Z) t.r = geo.muc[2];
-            tgeo[slot] = t;
+            rects[slot] = rc;
             // Render record (field map in vrs_internal.h); the colour goes to
             // the colour array (k_color).
             const double xi = floor(t.x0), yi = floor(t.y0);
@@ -200,7 +198,7 @@ __global__ void __launch_bounds__(256) k_color(GaussPtrs g, GeoViews views, floa
 // visible one -- rows are skipped by their visible counts and the column is
 // found by a binary search of the row's counts, all from the summed-area
 // table.
-__device__ inline void kth_tile(const GeoView& V, const TileGeo& tg, int k, int& tx, int& ty) {
+__device__ inline void kth_tile(const GeoView& V, const TileRect& tg, int k, int& tx, int& ty) {
     const int ncx = tg.ncx;
     if (!V.sat || tg.count == ncx * int(tg.ncy)) {
         tx = tg.tx0 + k % ncx;
@@ -227,21 +225,24 @@ __device__ inline void kth_tile(const GeoView& V, const TileGeo& tg, int k, int&
 
 // One wave per block owns 64 consecutive (view, Gaussian) slots and deals
 // their candidates out to its lanes 64 at a time, so every lane tests one
-// candidate per step whatever the spread of per-Gaussian counts.  The owner
-// of candidate j of the wave is found by a 6-step search of the wave's count
-// prefix in LDS; the lane then reads the owner's tile-test record directly
-// (the block's 64 records are one contiguous 14 KB span that stays in the
-// caches), which keeps LDS small enough for four waves per SIMD on the
-// latency-bound FP64 test.  n_inst[0]: candidates (from the scan),
+// candidate per step whatever the spread of per-Gaussian counts.  First each
+// lane derives its own slot's FP64 set-up from the Gaussian's parameters
+// into LDS (44 bytes read per Gaussian-view instead of a 176-byte record
+// written by K1 and read back here).  The owner of candidate j of the wave
+// is found by a 6-step search of the wave's count prefix in LDS; the lane
+// then reads the owner's set-up from LDS and its rectangle from K1.  n_inst[0]: candidates (from the scan),
 // n_inst[1]: kept instances.
 
-__global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const TileGeo* __restrict__ tgeo,
+template <int kViews>
+__global__ void __launch_bounds__(64) k_duplicate(GaussPtrs g, GeoViews views, Knobs kn, int n,
+                                                  const TileRect* __restrict__ rects,
                                                   const uint32_t* __restrict__ offsets,
                                                   const uint32_t* __restrict__ counts, size_t nslots,
                                                   uint32_t* __restrict__ n_inst, uint64_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ gids, size_t capacity, int kdepth) {
+                                                  uint32_t* __restrict__ gids, size_t capacity) {
     __shared__ uint32_t pre[65];
-    __shared__ GeoView vw[VRS_MAX_VIEWS];
+    __shared__ GeoView vw[kViews];  // the views the block's slots fall in, from v_lo
+    __shared__ TileGeo tgl[64];
     // No candidates, or more than the 32-bit offsets can address (the scan
     // then reports the overflow and leaves a total of 0): nothing to write.
     if (n_inst[0] == 0u) return;
@@ -250,7 +251,7 @@ __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const T
     const size_t nown = min(size_t(64), nslots - s0);
     const int v_lo = int(s0 / size_t(n)), v_hi = int((s0 + nown - 1) / size_t(n));
     for (int v = v_lo; v <= v_hi; ++v)
-        if (lane == 0) vw[v] = views.v[v];
+        if (lane == 0) vw[v - v_lo] = views.v[v];
     const size_t s = s0 + lane;
     const uint32_t c = s < nslots ? counts[s] : 0u;
     uint32_t incl = c;
@@ -261,6 +262,16 @@ __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const T
     }
     pre[lane] = incl - c;
     if (lane == 63) pre[64] = incl;
+    __syncthreads();
+    if (c > 0) {  // K1 counted candidates: the set-up succeeds as it did there
+        const int v = int(s / size_t(n));
+        Geo geo;
+        make_geo(load_gaussian(g, int(s - size_t(v) * size_t(n))), vw[v - v_lo], kn, views.ln_amin, geo);
+        // Per-Gaussian key depths (view z, distance) replace the per-tile
+        // depth: r then holds the key of every tile of the Gaussian.
+        if (kn.depth_mode == VRS_DEPTH_VIEW_Z) geo.tg.r = geo.muc[2];
+        tgl[lane] = geo.tg;
+    }
     __syncthreads();
     const uint32_t total = pre[64];
     const size_t base = offsets[s0];
@@ -279,15 +290,16 @@ __global__ void __launch_bounds__(64) k_duplicate(GeoViews views, int n, const T
             const size_t o = s0 + ow;
             const int v = int(o / size_t(n));
             const int i = int(o - size_t(v) * size_t(n));
-            const GeoView& V = vw[v];
-            const TileGeo tg = tgeo[o];
+            const GeoView& V = vw[v - v_lo];
+            const TileGeo& tg = tgl[ow];
+            const TileRect rc = rects[o];
             const int k = int(j - pre[ow]);
             int tx, ty;
-            kth_tile(V, tg, k, tx, ty);
+            kth_tile(V, rc, k, tx, ty);
             double bx0, by0, bx1, by1, depth;
             tile_box(V, tx, ty, bx0, by0, bx1, by1);
             kept = tile_test(tg, V, bx0, by0, bx1, by1, &depth);
-            if (kdepth != VRS_DEPTH_TILE_MAX) depth = tg.r;
+            if (kn.depth_mode != VRS_DEPTH_TILE_MAX) depth = tg.r;
             const uint64_t tile = uint64_t(V.tile_off) + uint64_t(ty) * V.ntx + tx;
             keys[cg] = kept ? ((tile << 32) | uint64_t(ord_f32(float(depth)))) : ~0ull;
             gids[cg] = uint32_t(i);
@@ -338,9 +350,9 @@ int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn
                       uint32_t* counts, int* status, hipStream_t s) {
     if (g.n == 0) return VRS_OK;
     const size_t nslots = size_t(g.n) * views.n;
-    TileGeo* tgeo = reinterpret_cast<TileGeo*>(reinterpret_cast<char*>(proj) + tgeo_offset_bytes(nslots));
+    TileRect* rects = reinterpret_cast<TileRect*>(reinterpret_cast<char*>(proj) + rect_offset_bytes(nslots));
     const int blocks = (g.n + 255) / 256;
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, s, g, views, kn, proj, tgeo, counts, status);
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(256), 0, s, g, views, kn, proj, rects, counts, status);
     // Groups of two views for a stereo pair (no work on padding views),
     // else four.
     if (views.n <= 2)
@@ -362,11 +374,17 @@ int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn,
     if (rc != VRS_OK) return rc;
     hipLaunchKernelGGL(k_dup_init, dim3(1), dim3(64), 0, s, n_inst, capacity, status);
     if (nslots == 0 || capacity == 0) return launch_status(hipGetLastError());
-    const TileGeo* tgeo =
-        reinterpret_cast<const TileGeo*>(reinterpret_cast<const char*>(proj) + tgeo_offset_bytes(nslots));
+    const TileRect* rects =
+        reinterpret_cast<const TileRect*>(reinterpret_cast<const char*>(proj) + rect_offset_bytes(nslots));
     const size_t blocks = (nslots + 63) / 64;
-    hipLaunchKernelGGL(k_duplicate, dim3(blocks), dim3(64), 0, s, views, g.n, tgeo, offsets, counts, nslots,
-                       n_inst, keys, gids, capacity, kn.depth_mode);
+    // 64 consecutive slots fall in at most two views when a view has 64
+    // Gaussians or more.
+    if (g.n >= 64)
+        hipLaunchKernelGGL(k_duplicate<2>, dim3(blocks), dim3(64), 0, s, g, views, kn, g.n, rects, offsets, counts,
+                           nslots, n_inst, keys, gids, capacity);
+    else
+        hipLaunchKernelGGL(k_duplicate<VRS_MAX_VIEWS>, dim3(blocks), dim3(64), 0, s, g, views, kn, g.n, rects,
+                           offsets, counts, nslots, n_inst, keys, gids, capacity);
     if (count_live) hipLaunchKernelGGL(k_count_live, dim3(256), dim3(256), 0, s, keys, n_inst, capacity);
     return launch_status(hipGetLastError());
 }

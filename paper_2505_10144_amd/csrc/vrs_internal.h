@@ -17,7 +17,7 @@ constexpr int kRec = VRS_RECORD_FLOATS;
 // (twice the blocks of 4096-key tiles: better latency hiding, 3 % faster
 // sort), 8-bit digits, at most 8 passes.
 constexpr int kSortThreads = 256;
-constexpr int kSortItemsPerLane = 8;
+constexpr int kSortItemsPerLane = 12;
 constexpr int kSortTile = kSortThreads * kSortItemsPerLane;
 constexpr int kRadix = 256;
 constexpr int kMaxPasses = 8;
@@ -54,12 +54,12 @@ enum RecField : int {
 };
 
 // Layout of the `proj` buffer for nslots = n_views * n (view-major) slots:
-// the FP32 render records, then the FP64 tile-test records (192 bytes
+// the FP32 render records, then the candidate tile rectangles (16 bytes
 // each), then one float4 colour (r, g, b, 0) per slot.
-constexpr size_t kTileGeoBytes = 192;
-__host__ __device__ inline size_t tgeo_offset_bytes(size_t nslots) { return nslots * kRec * sizeof(float); }
+constexpr size_t kTileRectBytes = 16;
+__host__ __device__ inline size_t rect_offset_bytes(size_t nslots) { return nslots * kRec * sizeof(float); }
 __host__ __device__ inline size_t colour_offset_bytes(size_t nslots) {
-    return nslots * (kRec * sizeof(float) + kTileGeoBytes);
+    return nslots * (kRec * sizeof(float) + kTileRectBytes);
 }
 __host__ __device__ inline const float4* colour_array(const float* proj, size_t nslots) {
     return reinterpret_cast<const float4*>(reinterpret_cast<const char*>(proj) + colour_offset_bytes(nslots));

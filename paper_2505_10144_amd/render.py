@@ -301,8 +301,8 @@ class Renderer:
 
     def colours(self) -> torch.Tensor:
         """[V][n][4] float32: each Gaussian's colour (r, g, b, 0) per view,
-        after the render and tile-test records in `proj`."""
-        off = self.V * self.n * (L.VRS_RECORD_FLOATS * 4 + L.TILEGEO_BYTES)
+        after the render records and tile rectangles in `proj`."""
+        off = self.V * self.n * (L.VRS_RECORD_FLOATS * 4 + L.TILERECT_BYTES)
         return self.proj[off: off + self.V * self.n * 16].view(torch.float32).view(self.V, self.n, 4)
 
 

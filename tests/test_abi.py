@@ -50,7 +50,7 @@ def test_workspace_size_stereo_layout():
     assert rc == 0
     assert s.tiles_total == 2 * 65 * 69                     # 32x32 sort tiles per eye
     assert s.items_max == 2 * 4 * 65 * 69
-    assert s.proj_bytes == 2 * 500_000 * (128 + 192 + 16)
+    assert s.proj_bytes == 2 * 500_000 * (128 + 16 + 16)  # record, tile rectangle, colour
     assert s.counts_bytes == 2 * 500_000 * 4
     pre = 2 * 4 * 2064 * 2208 * 4                            # pre-compose images
     # ... then the longest-first ordering of the work items: a 256-byte

@@ -399,12 +399,15 @@ def test_record_colours_and_alpha(R):
     record's mean image point and opacity equal the oracle's."""
     scene, cams, fovs, params = synth.config_stereo(6, n=3000, width=256, height=224)
     r, g = _stage_setup(R, scene, cams, fovs, params)
-    rec = r.records().cpu().numpy().astype(np.float64)
+    # Records of culled slots are never written: only valid rows are read.
+    rec_all = r.records().cpu().numpy()
     cols = r.colours().cpu().numpy().astype(np.float64)
     from oracle.render import preprocess_view
     for v, cam in enumerate(cams):
         pre = preprocess_view(scene, cam, params)
         ok = pre["valid"]
+        rec = np.zeros(rec_all.shape, np.float64)
+        rec[v, ok] = rec_all[v, ok]
         np.testing.assert_allclose(cols[v, ok, :3], pre["color"][ok], atol=2e-6)
         assert np.all(cols[v, :, 3] == 0.0)
         x0 = rec[v, ok, 0] + rec[v, ok, 2]

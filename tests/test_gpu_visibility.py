@@ -24,18 +24,18 @@ def R():
     return render
 
 
-def _tilegeo_rects(r):
+def _tile_rects(r):
     """Candidate rectangle (tx0, ty0, ncx, ncy) and count per (view,
-    Gaussian) from the render's tile-test records."""
+    Gaussian) from the rectangles the render's preprocess stored."""
     from paper_2505_10144_amd import _lib as L
     nslots = r.V * r.n
     off = nslots * L.VRS_RECORD_FLOATS * 4
-    raw = r.proj[off:off + nslots * L.TILEGEO_BYTES].cpu().numpy().reshape(nslots, L.TILEGEO_BYTES)
-    tx0 = raw[:, 176:180].view(np.int32)[:, 0]
-    ty0 = raw[:, 180:184].view(np.int32)[:, 0]
-    ncx = raw[:, 184:186].view(np.uint16)[:, 0].astype(np.int64)
-    ncy = raw[:, 186:188].view(np.uint16)[:, 0].astype(np.int64)
-    cnt = raw[:, 188:192].view(np.int32)[:, 0]
+    raw = r.proj[off:off + nslots * L.TILERECT_BYTES].cpu().numpy().reshape(nslots, L.TILERECT_BYTES)
+    tx0 = raw[:, 0:4].view(np.int32)[:, 0]
+    ty0 = raw[:, 4:8].view(np.int32)[:, 0]
+    ncx = raw[:, 8:10].view(np.uint16)[:, 0].astype(np.int64)
+    ncy = raw[:, 10:12].view(np.uint16)[:, 0].astype(np.int64)
+    cnt = raw[:, 12:16].view(np.int32)[:, 0]
     return tx0, ty0, ncx, ncy, cnt
 
 
@@ -64,7 +64,7 @@ def test_visibility_culling_matches_oracle(R, case):
     ref = oracle.render(scene, cams, fovs, params,
                         OracleOptions(alternatives=True, workers=workers()), masks=masks)
     # Counts: exactly the visible tiles of each Gaussian's rectangle.
-    tx0, ty0, ncx, ncy, cnt = _tilegeo_rects(r)
+    tx0, ty0, ncx, ncy, cnt = _tile_rects(r)
     counts = r.counts[:r.V * r.n].cpu().numpy().astype(np.int64)
     for v in range(len(cams)):
         sl = slice(v * scene.n, (v + 1) * scene.n)
