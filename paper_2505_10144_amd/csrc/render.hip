@@ -500,6 +500,69 @@ __global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __
     }
 }
 
+// K7 with 16-byte accesses, for views whose width is a multiple of 4: a
+// thread owns a 4x4 pixel block (one 16x16 subtile, so one class decides
+// it).  Per row and plane it loads one float4 and takes the pixels left and
+// right of it from the neighbouring lanes (loading them only at the wave's
+// two ends).  One block covers 256x16 pixels: 64 lanes x 4 columns, 4 waves
+// x 4 rows, with the same XCD-aware block order as k_compose.  The
+// arithmetic is k_compose's, term for term.
+__global__ void __launch_bounds__(256) k_compose4(RenderView V, const uint8_t* __restrict__ cls, uint32_t ntiles,
+                                                  uint32_t per_xcd) {
+    const uint32_t tid = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+    if (tid >= ntiles) return;
+    const uint32_t ntx = uint32_t(V.W + 255) / 256;
+    const int lane = int(threadIdx.x & 63);
+    const int x = int(tid % ntx) * 256 + 4 * lane;
+    const int y0 = (int(tid / ntx) * 4 + int(threadIdx.x >> 6)) * 4;
+    if (y0 >= V.H) return;  // whole wave
+    const bool act = x < V.W;
+    const int xc = act ? x : V.W - 4;  // lanes past the edge load in bounds, store nothing
+    const size_t plane = size_t(V.W) * size_t(V.H);
+    const int xl = max(xc - 1, 0), xr = min(xc + 4, V.W - 1);
+    int ry[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) ry[r] = min(max(y0 - 1 + r, 0), V.H - 1);
+    const uint8_t c = cls[V.cls_off + size_t(y0 >> 4) * V.ntx16 + (xc >> 4)];
+    const bool low = c == VRS_CLASS_LOW;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float* p = V.pre + k * plane;
+        float4 h[6], mid[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const float* row = p + size_t(ry[r]) * V.W;
+            const float4 v = *reinterpret_cast<const float4*>(row + xc);
+            // Left neighbour: lane - 1's last pixel (or the clamped pixel at
+            // the image edge, or a load at the wave's first lane).
+            const float up = __shfl_up(v.w, 1);
+            const float dn = __shfl_down(v.x, 1);
+            float left = lane > 0 ? up : row[xl];
+            if (xc == 0) left = v.x;
+            float right = (lane < 63 && xc + 4 < V.W) ? dn : row[xr];
+            if (!act) right = v.w;
+            h[r].x = fmaf(1.f, left, fmaf(2.f, v.x, v.y));
+            h[r].y = fmaf(1.f, v.x, fmaf(2.f, v.y, v.z));
+            h[r].z = fmaf(1.f, v.y, fmaf(2.f, v.z, v.w));
+            h[r].w = fmaf(1.f, v.z, fmaf(2.f, v.w, right));
+            mid[r] = v;
+        }
+        if (!act) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (y0 + r >= V.H) break;
+            float4 o = mid[r + 1];
+            if (low) {
+                o.x = fmaf(1.f, h[r + 2].x, fmaf(2.f, h[r + 1].x, h[r].x)) * (1.f / 16.f);
+                o.y = fmaf(1.f, h[r + 2].y, fmaf(2.f, h[r + 1].y, h[r].y)) * (1.f / 16.f);
+                o.z = fmaf(1.f, h[r + 2].z, fmaf(2.f, h[r + 1].z, h[r].z)) * (1.f / 16.f);
+                o.w = fmaf(1.f, h[r + 2].w, fmaf(2.f, h[r + 1].w, h[r].w)) * (1.f / 16.f);
+            }
+            *reinterpret_cast<float4*>(V.out + k * plane + size_t(y0 + r) * V.W + x) = o;
+        }
+    }
+}
+
 // Blocks of a persistent launch: enough to fill every CU at the kernel's
 // occupancy, never more than the work items.
 template <typename K>
@@ -670,6 +733,13 @@ int launch_compose(const RenderViews& views, const uint8_t* cls, hipStream_t s) 
     for (int v = 0; v < views.n; ++v) {
         const RenderView& V = views.v[v];
         if (!V.foveated) continue;
+        if (V.W % 4 == 0 && (reinterpret_cast<uintptr_t>(V.pre) & 15u) == 0 &&
+            (reinterpret_cast<uintptr_t>(V.out) & 15u) == 0) {
+            const uint32_t ntiles = uint32_t((V.W + 255) / 256) * uint32_t((V.H + 15) / 16);
+            const uint32_t per = (ntiles + kXcds - 1) / kXcds;
+            hipLaunchKernelGGL(k_compose4, dim3(per * kXcds), dim3(256), 0, s, V, cls, ntiles, per);
+            continue;
+        }
         const uint32_t ntiles = uint32_t((V.W + 63) / 64) * uint32_t((V.H + 4 * kComposeRows - 1) / (4 * kComposeRows));
         const uint32_t per = (ntiles + kXcds - 1) / kXcds;
         hipLaunchKernelGGL(k_compose, dim3(per * kXcds), dim3(256), 0, s, V, cls, ntiles, per);
