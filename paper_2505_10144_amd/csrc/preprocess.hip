@@ -266,10 +266,15 @@ __global__ void __launch_bounds__(64) k_duplicate(GaussPtrs g, GeoViews views, K
     if (c > 0) {  // K1 counted candidates: the set-up succeeds as it did there
         const int v = int(s / size_t(n));
         Geo geo;
-        make_geo(load_gaussian(g, int(s - size_t(v) * size_t(n))), vw[v - v_lo], kn, views.ln_amin, geo);
-        // Per-Gaussian key depths (view z, distance) replace the per-tile
-        // depth: r then holds the key of every tile of the Gaussian.
-        if (kn.depth_mode == VRS_DEPTH_VIEW_Z) geo.tg.r = geo.muc[2];
+        if (make_geo(load_gaussian(g, int(s - size_t(v) * size_t(n))), vw[v - v_lo], kn, views.ln_amin, geo)) {
+            // Per-Gaussian key depths (view z, distance) replace the per-tile
+            // depth: r then holds the key of every tile of the Gaussian.
+            if (kn.depth_mode == VRS_DEPTH_VIEW_Z) geo.tg.r = geo.muc[2];
+        } else {
+            // (Not reached.)  Every tile test then fails: dead keys.
+            geo.tg.x0 = geo.tg.y0 = __builtin_nan("");
+            geo.tg.kappa = -1.0;
+        }
         tgl[lane] = geo.tg;
     }
     __syncthreads();
