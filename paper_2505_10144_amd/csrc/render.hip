@@ -633,7 +633,7 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
 // The order within a run depends on timing, which does not matter: every
 // item writes only its own pixels.
 constexpr int kOrderThreads = 1024;
-constexpr int kOrderPer = 8;  // items a thread has in flight
+constexpr int kOrderPer = 16;  // items a thread has in flight
 
 __device__ inline uint32_t item_cost_key(uint32_t it, const uint32_t* __restrict__ ranges, const RenderViews& views) {
     const RenderView& V = views.v[item_view(it)];
@@ -656,11 +656,28 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
     __shared__ uint32_t wsum[4];
     const int t = threadIdx.x;
     const uint32_t n = min(*count_dev, n_max);
+    constexpr uint32_t kChunk = uint32_t(kOrderThreads * kOrderPer);
     if (t < 256) cnt[t] = 0;
     __syncthreads();
     // Each thread keeps kOrderPer items (and their list-range loads) in
-    // flight at a time.
-    for (uint32_t c0 = 0; c0 < n; c0 += uint32_t(kOrderThreads * kOrderPer)) {
+    // flight at a time.  The first chunk's items and keys stay in registers
+    // for the scatter (the only chunk when there are at most kChunk items);
+    // later chunks are loaded again.
+    uint32_t it0[kOrderPer], key0[kOrderPer];
+#pragma unroll
+    for (int j = 0; j < kOrderPer; ++j) {
+        const uint32_t i = uint32_t(j * kOrderThreads + t);
+        it0[j] = i < n ? items[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kOrderPer; ++j) {
+        key0[j] = 0u;
+        if (uint32_t(j * kOrderThreads + t) < n) {
+            key0[j] = item_cost_key(it0[j], ranges, views);
+            atomicAdd(&cnt[key0[j]], 1u);
+        }
+    }
+    for (uint32_t c0 = kChunk; c0 < n; c0 += kChunk) {
         uint32_t it[kOrderPer];
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j) {
@@ -692,7 +709,10 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
         cnt[t] = pre + v - x;
     }
     __syncthreads();
-    for (uint32_t c0 = 0; c0 < n; c0 += uint32_t(kOrderThreads * kOrderPer)) {
+#pragma unroll
+    for (int j = 0; j < kOrderPer; ++j)
+        if (uint32_t(j * kOrderThreads + t) < n) out[atomicAdd(&cnt[key0[j]], 1u)] = it0[j];
+    for (uint32_t c0 = kChunk; c0 < n; c0 += kChunk) {
         uint32_t it[kOrderPer];
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j) {

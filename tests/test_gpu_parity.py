@@ -17,7 +17,7 @@ import synth
 from oracle import fovea as ofov
 from oracle import tiles as otiles
 from oracle.render import OracleOptions
-from parity_check import check_render, ref_render
+from parity_check import check_render, ref_render, workers
 
 pytestmark = pytest.mark.gpu
 
@@ -247,6 +247,49 @@ def test_instances_and_keys_match_oracle(R):
         oc = np.bincount(ref["gids"][inview].astype(np.int64), minlength=scene.n)
         assert np.all(cnt[v] >= oc)
         assert np.array_equal(cnt[v] > 0, ref["pre"][v]["valid"] & (cnt[v] > 0))
+
+
+def test_instances_and_keys_full_stereo_frame(R):
+    """Instantiation at full size (500k Gaussians, 2 x 2064x2208): the GPU's
+    instance set equals the oracle's up to borderline tile tests (an
+    instance only one side has must be within 1e-9 of the alpha_min cut in
+    ln alpha by the oracle's own tile test), and the depth bits of shared
+    instances differ by at most one float32 ulp."""
+    scene, cams, fovs, params = synth.config_stereo(0)
+    print(f"[keys] full stereo frame n={scene.n}", flush=True)
+    r, g = _stage_setup(R, scene, cams, fovs, params)
+    n_cand, n_kept = (int(x) for x in r.n_inst.cpu().tolist())
+    keys = r.keys[:n_cand].cpu().numpy().view(np.uint64)
+    gids = r.gids[:n_cand].cpu().numpy().view(np.uint32).astype(np.int64)
+    live = keys != np.uint64(0xFFFFFFFFFFFFFFFF)
+    assert int(live.sum()) == n_kept
+    keys, gids = keys[live], gids[live]
+    ref = oracle.render(scene, cams, fovs, params, OracleOptions(shade=False, workers=workers()))
+    s32 = np.uint64(32)
+    gtile = (keys >> s32).astype(np.int64)
+    gcode = gtile * (1 << 20) + gids
+    gbits = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    ocode = ref["inst_tile"] * (1 << 20) + ref["inst_gid"]
+    obits = otiles.ord_f32(ref["inst_depth"]).astype(np.int64)
+    _, gi, oi = np.intersect1d(gcode, ocode, assume_unique=True, return_indices=True)
+    only_o = np.setdiff1d(np.arange(len(ocode)), oi)
+    only_g = np.setdiff1d(np.arange(len(gcode)), gi)
+    d = np.abs(gbits[gi] - obits[oi])
+    print(f"[keys] {len(gi)} shared instances ({int((d > 0).sum())} one ulp apart), {len(only_o)} oracle-only, "
+          f"{len(only_g)} GPU-only", flush=True)
+    assert len(gi) > 2_000_000
+    assert np.all(ref["inst_border"][only_o])
+    ln_amin = math.log(np.float64(params.alpha_min))
+    for k in only_g:
+        t = int(gtile[k])
+        v = 0 if t < ref["view_offsets"][1] else 1
+        pre, grid, gg = ref["pre"][v], ref["grids"][v], int(gids[k])
+        bx0, by0, bx1, by1 = grid.boxes(np.array([t - ref["view_offsets"][v]]))
+        res = otiles.quad_test(cams[v], pre["f"], pre["u"][[gg]], pre["E"][[gg]], pre["C"][[gg]], pre["x0"][[gg]],
+                               pre["y0"][[gg]], bx0, by0, bx1, by1)
+        lnah = math.log(pre["sigma"][gg]) - 0.5 * float(res["D2min"][0])
+        assert abs(lnah - ln_amin) < 1e-9, (t, gg, lnah - ln_amin)
+    assert d.max() <= 1 and (d > 0).mean() < 1e-3
 
 
 def test_sort_pairs_bit_exact_on_gpu_keys(R):
