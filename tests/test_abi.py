@@ -138,3 +138,49 @@ def test_noalloc_sort_rejects_requests_beyond_its_scratch():
     assert lib.vrs_sort_pairs_noalloc(None, None, ctypes.c_void_p(16), 10, 40, None, None) == L.VRS_ERR_INVALID_ARG
     # The scratch holds the workspace of the largest request.
     assert lib.vrs_sort_pairs_workspace_size(L.VRS_SORT_NOALLOC_MAX_PAIRS) < 40 << 20
+
+
+def test_training_and_two_pass_entry_points_validate_arguments():
+    """The two-pass, loss, Adam and backward entry points reject bad
+    arguments on the host, before any device work."""
+    lib = L.load()
+    bad = L.VRS_ERR_INVALID_ARG
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(256)  # never dereferenced: validation fails first
+    cam = L.camera_array([synth.camera_translate((0, 0, -3), 90, 64, 64)])
+    fov = L.fovea_array([synth.fovea_off()])
+    p = L.make_params(synth.default_params())
+    ptrs = (ctypes.c_void_p * 1)(256)
+    nulls = (ctypes.c_void_p * 1)(0)
+    # Two-pass: a plan is required; the centre box must lie in the image.
+    ccam, lcam = (L.vrs_camera * 1)(), (L.vrs_camera * 1)()
+    boxes = (ctypes.c_int32 * 4)()
+    assert lib.vrs_two_pass_views(cam, fov, 1, ctypes.byref(p), null, ccam, boxes, lcam, null) == bad
+    assert lib.vrs_two_pass_views(cam, fov, 0, ctypes.byref(p), fake, ccam, boxes, lcam, null) == bad
+    assert lib.vrs_two_pass_compose(cam, fov, 1, boxes, nulls, nulls, nulls, null) == bad
+    outside = (ctypes.c_int32 * 4)(0, 0, 65, 64)
+    assert lib.vrs_two_pass_compose(cam, fov, 1, outside, ptrs, ptrs, ptrs, null) == bad
+    # Loss: workspace of one FP64 partial per block, 8-byte aligned.
+    assert lib.vrs_loss_workspace_size(0) == 0
+    need = lib.vrs_loss_workspace_size(1)
+    assert need > 0 and lib.vrs_loss_workspace_size(3) == 3 * need
+    assert lib.vrs_loss_l1l2(cam, 1, ptrs, ptrs, ptrs, fake, null, need, null) == bad
+    assert lib.vrs_loss_l1l2(cam, 1, ptrs, ptrs, ptrs, fake, ctypes.c_void_p(260), need, null) == bad
+    assert lib.vrs_loss_l1l2(cam, 1, ptrs, ptrs, ptrs, fake, fake, need - 8, null) == bad
+    assert lib.vrs_loss_l1l2(cam, 0, ptrs, ptrs, ptrs, fake, fake, need, null) == bad
+    # Adam: an empty update is a no-op; hyper-parameters are checked.
+    assert lib.vrs_adam_step(null, null, null, null, 0, 1e-3, 0.9, 0.999, 1e-15, 1, null) == L.VRS_OK
+    ok_args = dict(lr=1e-3, b1=0.9, b2=0.999, eps=1e-15, step=1)
+    for change in (dict(b1=1.0), dict(b2=-0.1), dict(eps=0.0), dict(step=0), dict(lr=float("nan"))):
+        a = dict(ok_args, **change)
+        assert lib.vrs_adam_step(fake, fake, fake, fake, 10, a["lr"], a["b1"], a["b2"], a["eps"], a["step"],
+                                 null) == bad, change
+    assert lib.vrs_adam_step(null, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-15, 1, null) == bad
+    # Backward: Gaussian parameters and buffers are checked first.
+    assert lib.vrs_backward_workspace_size(10, cam, fov, 1, ctypes.byref(p)) > 0
+    g = L.vrs_gaussians()
+    g.n = 5
+    g.sh_degree = 3
+    grads = L.vrs_gaussian_grads()
+    assert lib.vrs_render_backward(ctypes.byref(g), null, null, null, cam, fov, 1, ctypes.byref(p), null, 0, ptrs,
+                                   ptrs, ctypes.byref(grads), null, 0, null, null) == bad
