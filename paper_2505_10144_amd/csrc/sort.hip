@@ -181,12 +181,18 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __r
     __syncthreads();
     const size_t n = n_eff(n_dev, capacity);
     const size_t base = size_t(blockIdx.x) * kSortTile;
+    // Every load is issued before the first count, so the wave waits for
+    // memory once rather than once per key.
+    uint64_t key[kSortItemsPerLane];
+#pragma unroll
     for (int k = 0; k < kSortItemsPerLane; ++k) {
         const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
-        if (idx < n) {
-            const uint64_t key = keys[idx];
-            if (!(drop && key == kDeadKey)) atomicAdd(&cnt[uint32_t(key >> shift) & 0xFFu], 1u);
-        }
+        key[k] = idx < n ? keys[idx] : kDeadKey;
+    }
+#pragma unroll
+    for (int k = 0; k < kSortItemsPerLane; ++k) {
+        const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
+        if (idx < n && !(drop && key[k] == kDeadKey)) atomicAdd(&cnt[uint32_t(key[k] >> shift) & 0xFFu], 1u);
     }
     __syncthreads();
     hist[size_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
@@ -225,12 +231,19 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     uint32_t rank[kSortItemsPerLane];
     bool live[kSortItemsPerLane];
     const uint64_t lt = lanemask_lt();
+    // All loads first (the ranking below orders LDS accesses with wave
+    // fences, which would otherwise hold each load until the previous step).
 #pragma unroll
     for (int it = 0; it < kSortItemsPerLane; ++it) {
         const size_t idx = base + size_t(it) * 64 + lane;
         const bool in = idx < n;
         key[it] = in ? kin[idx] : 0ull;
         val[it] = in ? vin[idx] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItemsPerLane; ++it) {
+        const size_t idx = base + size_t(it) * 64 + lane;
+        const bool in = idx < n;
         const bool ok = in && !(drop && key[it] == kDeadKey);
         live[it] = ok;
         const uint32_t d = uint32_t(key[it] >> shift) & 0xFFu;
@@ -301,14 +314,18 @@ __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* _
     const size_t n = n_eff(n_dev, capacity);
     const size_t base = size_t(blockIdx.x) * kSortTile;
     uint32_t live = 0;
+    uint64_t key[kSortItemsPerLane];
+#pragma unroll
+    for (int k = 0; k < kSortItemsPerLane; ++k) {  // all loads first
+        const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
+        key[k] = idx < n ? keys[idx] : kDeadKey;
+    }
+#pragma unroll
     for (int k = 0; k < kSortItemsPerLane; ++k) {
         const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
-        if (idx < n) {
-            const uint64_t key = keys[idx];
-            if (!(drop && key == kDeadKey)) {
-                ++live;
-                for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][uint32_t(key >> (8 * p)) & 0xFFu], 1u);
-            }
+        if (idx < n && !(drop && key[k] == kDeadKey)) {
+            ++live;
+            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][uint32_t(key[k] >> (8 * p)) & 0xFFu], 1u);
         }
     }
     if (live_out) {  // uniform
