@@ -116,8 +116,10 @@ struct BWindow {
 
 // Fixed-point accumulation of one contribution (see above).  Returns false
 // when it does not fit the accumulator's range; the caller adds it elsewhere.
-__device__ inline bool fixed_add(unsigned long long* acc, int* scale, float g) {
-    int e = *scale;
+// `e` is the scale as read before (a scale, once set, never changes while
+// its entry is in the ring; if it was still unset the compare-and-swap
+// below returns whichever scale won).
+__device__ inline bool fixed_add(unsigned long long* acc, int* scale, int e, float g) {
     if (e == kUnset) {
         int fe;
         frexpf(g, &fe);  // |g| < 2^fe
@@ -178,7 +180,10 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
     // Value-major, so that the lanes of one atomic instruction (one value of
     // different entries) fall in different banks.
     __shared__ unsigned long long acc[kG][kRing];
-    __shared__ int acc_scale[kG][kRing];
+    // Entry-major, so that a queue round reads an entry's twelve scales
+    // with three 16-byte loads.
+    static_assert(kG % 4 == 0, "scales are read four at a time");
+    __shared__ __align__(16) int acc_scale[kRing][kG];
     __shared__ float4 queue[kBwdThreads / 64][kQueue];
 
     // The work item (the plan's, as rendered by the forward pass).
@@ -278,7 +283,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         if (pend) {
             const float gc = fmaf(gr[0], pc.x, fmaf(gr[1], pc.y, gr[2] * pc.z));
             const float w = p_T * p_ea;
-            const float inv1 = 1.f / (1.f - p_ea);
+            const float inv1 = __builtin_amdgcn_rcpf(1.f - p_ea);  // 1 - alpha >= 0.01
             // dL/dalpha = g_rgb . (c T - S / (1 - alpha)) + g_a T_fin / (1 - alpha),
             // S = C_fin - C_<=i (+ background T_fin, folded into gback).
             rdA = fmaf(gback - (gCf - fmaf(w, gc, D)), inv1, p_T * gc);
@@ -344,10 +349,13 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             const float z2 = fmaf(M10, dx, M11 * dy);
             const float h = fmaf(a3x, dx, fmaf(a3y, dy, 1.f));
             const float q = fmaf(z1, z1, z2 * z2);
-            const float ih = 1.f / h;
+            // Hardware reciprocal and exp2: h > 0 for a blended pair, and
+            // both exponents below are at most log2(255) in magnitude (the
+            // pair passed the alpha_min test), inside the normal range.
+            const float ih = __builtin_amdgcn_rcpf(h);
             const float ih2 = ih * ih;
             const float E = q * ih2;
-            const float a_un = exp2f(e[2].x - E);  // unclamped alpha
+            const float a_un = __builtin_amdgcn_exp2f(e[2].x - E);  // unclamped alpha
             if (a_un < amax) {
                 const float gE = dA * (-0.69314718055994531f) * a_un;  // dL/dE
                 const float cz = 2.f * gE * ih2;
@@ -360,13 +368,21 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
                 g[G_A3 + 1] = ch * dy;
                 g[G_XY + 0] = -(cz * fmaf(z1, M00, z2 * M10) + ch * a3x);
                 g[G_XY + 1] = -(cz * fmaf(z1, M01, z2 * M11) + ch * a3y);
-                g[G_SIG] = dA * exp2f(-E);
+                g[G_SIG] = dA * __builtin_amdgcn_exp2f(-E);
             }
             float* dst = vgrad + size_t(gid) * kG;
+            int sc[kG];
+            if (in_ring) {
+#pragma unroll
+                for (int k4 = 0; k4 < kG / 4; ++k4) {
+                    const int4 s4 = reinterpret_cast<const int4*>(acc_scale[sl])[k4];
+                    sc[4 * k4] = s4.x; sc[4 * k4 + 1] = s4.y; sc[4 * k4 + 2] = s4.z; sc[4 * k4 + 3] = s4.w;
+                }
+            }
 #pragma unroll
             for (int k = 0; k < kG; ++k) {
                 if (g[k] == 0.f) continue;
-                if (!in_ring || !fixed_add(&acc[k][sl], &acc_scale[k][sl], g[k])) unsafeAtomicAdd(dst + k, g[k]);
+                if (!in_ring || !fixed_add(&acc[k][sl], &acc_scale[sl][k], sc[k], g[k])) unsafeAtomicAdd(dst + k, g[k]);
             }
         }
         qhead += nq;
@@ -416,7 +432,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
             // Flush the batch that leaves the ring.
             for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
                 const int s = base + w / kG, k = w % kG;
-                const int sc = acc_scale[k][s];
+                const int sc = acc_scale[s][k];
                 if (sc != kUnset && acc[k][s] != 0ull)
                     unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[5][s].z)) * kG + k],
                                     fixed_value(acc[k][s], sc));
@@ -433,7 +449,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         }
         for (int w = t; w < kBwdBatch * kG; w += kBwdThreads) {
             acc[w % kG][base + w / kG] = 0ull;
-            acc_scale[w % kG][base + w / kG] = kUnset;
+            acc_scale[base + w / kG][w % kG] = kUnset;
         }
         last_b0 = b0;
         staged_end = b0 + uint32_t(nb);
@@ -495,7 +511,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_render_bwd(const float* __restr
         const int s = w / kG, k = w % kG;
         const uint32_t a = first + (uint32_t(s) + uint32_t(kRing) - first % uint32_t(kRing)) % uint32_t(kRing);
         if (a >= staged_end) continue;
-        const int sc = acc_scale[k][s];
+        const int sc = acc_scale[s][k];
         if (sc != kUnset && acc[k][s] != 0ull)
             unsafeAtomicAdd(&vgrad[size_t(__float_as_uint(ring[5][s].z)) * kG + k], fixed_value(acc[k][s], sc));
     }

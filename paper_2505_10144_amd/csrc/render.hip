@@ -635,9 +635,7 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderPer = 16;  // items a thread has in flight
 
-__device__ inline uint32_t item_cost_key(uint32_t it, const uint32_t* __restrict__ ranges, const RenderViews& views) {
-    const RenderView& V = views.v[item_view(it)];
-    const uint2 rg = reinterpret_cast<const uint2*>(ranges)[V.tile_off + item_tile(it)];
+__device__ inline uint32_t cost_key(uint2 rg) {
     const uint32_t c = rg.y - rg.x;
     uint32_t b = 0;
     if (c != 0) {
@@ -654,11 +652,25 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
                                                                RenderViews views, uint32_t* __restrict__ out) {
     __shared__ uint32_t cnt[256];
     __shared__ uint32_t wsum[4];
+    __shared__ uint32_t toff[VRS_MAX_VIEWS];  // each view's first global tile
     const int t = threadIdx.x;
     const uint32_t n = min(*count_dev, n_max);
     constexpr uint32_t kChunk = uint32_t(kOrderThreads * kOrderPer);
     if (t < 256) cnt[t] = 0;
+    if (t < views.n) toff[t] = views.v[t].tile_off;
     __syncthreads();
+    const uint2* rgs = reinterpret_cast<const uint2*>(ranges);
+    // A chunk's items, then their list ranges, each as one batch of loads.
+    auto keys_of = [&](uint32_t c0, const uint32_t (&it)[kOrderPer], uint32_t (&key)[kOrderPer]) {
+        uint2 rg[kOrderPer];
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j) {
+            rg[j] = make_uint2(0u, 0u);
+            if (c0 + uint32_t(j * kOrderThreads + t) < n) rg[j] = rgs[toff[item_view(it[j])] + item_tile(it[j])];
+        }
+#pragma unroll
+        for (int j = 0; j < kOrderPer; ++j) key[j] = cost_key(rg[j]);
+    };
     // Each thread keeps kOrderPer items (and their list-range loads) in
     // flight at a time.  The first chunk's items and keys stay in registers
     // for the scatter (the only chunk when there are at most kChunk items);
@@ -669,24 +681,21 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
         const uint32_t i = uint32_t(j * kOrderThreads + t);
         it0[j] = i < n ? items[i] : 0u;
     }
+    keys_of(0u, it0, key0);
 #pragma unroll
-    for (int j = 0; j < kOrderPer; ++j) {
-        key0[j] = 0u;
-        if (uint32_t(j * kOrderThreads + t) < n) {
-            key0[j] = item_cost_key(it0[j], ranges, views);
-            atomicAdd(&cnt[key0[j]], 1u);
-        }
-    }
+    for (int j = 0; j < kOrderPer; ++j)
+        if (uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[key0[j]], 1u);
     for (uint32_t c0 = kChunk; c0 < n; c0 += kChunk) {
-        uint32_t it[kOrderPer];
+        uint32_t it[kOrderPer], key[kOrderPer];
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j) {
             const uint32_t i = c0 + uint32_t(j * kOrderThreads + t);
             it[j] = i < n ? items[i] : 0u;
         }
+        keys_of(c0, it, key);
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j)
-            if (c0 + uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[item_cost_key(it[j], ranges, views)], 1u);
+            if (c0 + uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[key[j]], 1u);
     }
     __syncthreads();
     // Exclusive scan of the 256 counts by the first four waves.
@@ -713,16 +722,16 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
     for (int j = 0; j < kOrderPer; ++j)
         if (uint32_t(j * kOrderThreads + t) < n) out[atomicAdd(&cnt[key0[j]], 1u)] = it0[j];
     for (uint32_t c0 = kChunk; c0 < n; c0 += kChunk) {
-        uint32_t it[kOrderPer];
+        uint32_t it[kOrderPer], key[kOrderPer];
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j) {
             const uint32_t i = c0 + uint32_t(j * kOrderThreads + t);
             it[j] = i < n ? items[i] : 0u;
         }
+        keys_of(c0, it, key);
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j)
-            if (c0 + uint32_t(j * kOrderThreads + t) < n)
-                out[atomicAdd(&cnt[item_cost_key(it[j], ranges, views)], 1u)] = it[j];
+            if (c0 + uint32_t(j * kOrderThreads + t) < n) out[atomicAdd(&cnt[key[j]], 1u)] = it[j];
     }
 }
 
