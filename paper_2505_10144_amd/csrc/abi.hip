@@ -12,7 +12,7 @@ int launch_status(hipError_t e) { return e == hipSuccess ? VRS_OK : VRS_ERR_HIP;
 // Launchers defined in the kernel translation units.
 int launch_preprocess(const GaussPtrs&, const GeoViews&, const Knobs&, float*, uint32_t*, int*, hipStream_t);
 int launch_duplicate(const GaussPtrs&, const GeoViews&, const Knobs&, const float*, const uint32_t*, uint64_t*,
-                     uint32_t*, size_t, uint32_t*, void*, int*, hipStream_t, bool);
+                     uint32_t*, size_t, uint32_t*, void*, int*, hipStream_t, bool, uint32_t*, size_t);
 size_t sort_ws_bytes(size_t capacity);
 int launch_sort_pairs(uint64_t*, uint32_t*, const uint32_t*, size_t, int, void*, int*, hipStream_t);
 int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*, bool, size_t, int, void*, int*,
@@ -22,7 +22,7 @@ int launch_sort_pairs_ex(uint64_t*, uint32_t*, const uint32_t*, const uint32_t*,
 // tile-test record (TileGeo, 192 bytes) that instantiation reads.
 constexpr size_t kProjBytesPerSlot = kRec * sizeof(float) + kTileRectBytes + 4 * sizeof(float);
 size_t dup_ws_bytes(size_t nslots) { return (nslots + scan_tmp_words(nslots) + 64) * sizeof(uint32_t); }
-int launch_tile_ranges(const uint64_t*, const uint32_t*, size_t, uint32_t, uint32_t*, hipStream_t);
+int launch_tile_ranges(const uint64_t*, const uint32_t*, size_t, uint32_t, uint32_t*, hipStream_t, bool = true);
 int launch_blend(const float*, uint32_t, const uint32_t*, const uint32_t*, const uint32_t*, uint32_t, uint32_t*, int,
                  int, const RenderViews&, const Knobs&, int, unsigned long long*, hipStream_t);
 uint32_t* order_counter(void* ws);
@@ -216,7 +216,8 @@ static int duplicate_impl(const vrs_gaussians* g, const vrs_camera* cams, const 
                           int32_t n_views, const vrs_params* p, const void* plan, const void* proj,
                           const uint32_t* counts,
                           uint64_t* keys, uint32_t* gids, size_t capacity, uint32_t* n_inst_dev, void* ws,
-                          size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream, bool count_live) {
+                          size_t ws_bytes, int32_t* status_dev, vrs_stream_t stream, bool count_live,
+                          uint32_t* clear = nullptr, size_t n_clear = 0) {
     int rc = check_gaussians(g);
     if (rc != VRS_OK) return rc;
     Layout L;
@@ -231,7 +232,7 @@ static int duplicate_impl(const vrs_gaussians* g, const vrs_camera* cams, const 
     if (plan && !aligned(plan, 256)) return VRS_ERR_INVALID_ARG;
     return launch_duplicate(gauss_ptrs(g), geo_views(cams, L, p, plan), knobs(p), static_cast<const float*>(proj), counts,
                             keys, gids, capacity, n_inst_dev, ws, status_dev, reinterpret_cast<hipStream_t>(stream),
-                            count_live);
+                            count_live, clear, n_clear);
 }
 
 extern "C" {
@@ -394,8 +395,9 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
     if (!ranges && L.tiles_total > 0) return VRS_ERR_INVALID_ARG;
     if (capacity > 0 && ws_bytes < sort_ws_bytes(capacity)) return VRS_ERR_INVALID_ARG;
     // The sort's first kernel counts the kept instances into n_inst_dev[1].
+    // Instantiation also clears the tile ranges that the sort fills in.
     rc = duplicate_impl(g, cams, foveas, n_views, p, plan, proj, counts, keys, gids, capacity, n_inst_dev, ws,
-                        ws_bytes, status_dev, stream, false);
+                        ws_bytes, status_dev, stream, false, ranges, size_t(L.tiles_total) * 2);
     if (rc != VRS_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (capacity > 0) {
@@ -404,7 +406,7 @@ int vrs_sort(const vrs_gaussians* g, const vrs_camera* cams, const vrs_fovea* fo
                                   key_bits_for(L.tiles_total), ws, status_dev, s, n_inst_dev + 1);
         if (rc != VRS_OK) return rc;
     }
-    return launch_tile_ranges(keys, n_inst_dev + 1, capacity, L.tiles_total, ranges, s);
+    return launch_tile_ranges(keys, n_inst_dev + 1, capacity, L.tiles_total, ranges, s, false);
 }
 
 }  // extern "C"

@@ -330,11 +330,16 @@ __global__ void __launch_bounds__(256) k_count_live(const uint64_t* __restrict__
     }
 }
 
-__global__ void k_dup_init(uint32_t* n_inst, size_t capacity, int* status) {
+// Also clears `clear` (n_clear words: the tile ranges the sort fills in
+// later, when the caller passes them), saving that launch.
+__global__ void k_dup_init(uint32_t* n_inst, size_t capacity, int* status, uint32_t* __restrict__ clear,
+                           size_t n_clear) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         n_inst[1] = 0;
         if (size_t(n_inst[0]) > capacity) set_status(status, VRS_ERR_CAPACITY);
     }
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_clear; i += size_t(gridDim.x) * blockDim.x)
+        clear[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -371,13 +376,16 @@ int launch_preprocess(const GaussPtrs& g, const GeoViews& views, const Knobs& kn
 // (the sort's first kernel counts the live keys anyway).
 int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn, const float* proj,
                      const uint32_t* counts, uint64_t* keys, uint32_t* gids, size_t capacity,
-                     uint32_t* n_inst, void* ws, int* status, hipStream_t s, bool count_live) {
+                     uint32_t* n_inst, void* ws, int* status, hipStream_t s, bool count_live, uint32_t* clear,
+                     size_t n_clear) {
     const size_t nslots = size_t(g.n) * size_t(views.n);
     uint32_t* offsets = static_cast<uint32_t*>(ws);
     uint32_t* tmp = offsets + nslots;
     int rc = launch_exclusive_scan(counts, offsets, nslots, n_inst, tmp, status, s);
     if (rc != VRS_OK) return rc;
-    hipLaunchKernelGGL(k_dup_init, dim3(1), dim3(64), 0, s, n_inst, capacity, status);
+    const size_t clear_blocks = (n_clear + 255) / 256;
+    hipLaunchKernelGGL(k_dup_init, dim3(clear_blocks == 0 ? 1 : (clear_blocks < 1024 ? clear_blocks : 1024)),
+                       dim3(256), 0, s, n_inst, capacity, status, clear, n_clear);
     if (nslots == 0 || capacity == 0) return launch_status(hipGetLastError());
     const TileRect* rects =
         reinterpret_cast<const TileRect*>(reinterpret_cast<const char*>(proj) + rect_offset_bytes(nslots));

@@ -505,7 +505,9 @@ __global__ void __launch_bounds__(256) k_compose(RenderView V, const uint8_t* __
 // it).  Per row and plane it loads one float4 and takes the pixels left and
 // right of it from the neighbouring lanes (loading them only at the wave's
 // two ends).  One block covers 256x16 pixels: 64 lanes x 4 columns, 4 waves
-// x 4 rows, with the same XCD-aware block order as k_compose.  The
+// x 4 rows, with the same XCD-aware block order as k_compose.  In a LOW
+// block the blend wrote each value to a 2x2 pixel group, so the block's
+// second and fourth rows repeat its first and third and are not loaded.  The
 // arithmetic is k_compose's, term for term.
 __global__ void __launch_bounds__(256) k_compose4(RenderView V, const uint8_t* __restrict__ cls, uint32_t ntiles,
                                                   uint32_t per_xcd) {
@@ -529,10 +531,13 @@ __global__ void __launch_bounds__(256) k_compose4(RenderView V, const uint8_t* _
     for (int k = 0; k < 4; ++k) {
         const float* p = V.pre + k * plane;
         float4 h[6], mid[6];
+        float4 vprev = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
             const float* row = p + size_t(ry[r]) * V.W;
-            const float4 v = *reinterpret_cast<const float4*>(row + xc);
+            float4 v = vprev;
+            if (!low || r == 0 || r == 1 || r == 3 || r == 5) v = *reinterpret_cast<const float4*>(row + xc);
+            vprev = v;
             // Left neighbour: lane - 1's last pixel (or the clamped pixel at
             // the image edge, or a load at the wave's first lane).
             const float up = __shfl_up(v.w, 1);

@@ -491,10 +491,13 @@ int launch_sort_pairs(uint64_t* keys, uint32_t* vals, const uint32_t* n_dev, siz
     return launch_sort_pairs_ex(keys, vals, n_dev, n_dev, false, capacity, key_bits, ws, err, s, nullptr);
 }
 
+// With clear false the caller has zeroed `ranges` already.
 int launch_tile_ranges(const uint64_t* keys, const uint32_t* n_dev, size_t capacity, uint32_t tiles_total,
-                       uint32_t* ranges, hipStream_t s) {
-    int rc = launch_fill_u32(ranges, size_t(tiles_total) * 2, 0u, s);
-    if (rc != VRS_OK) return rc;
+                       uint32_t* ranges, hipStream_t s, bool clear) {
+    if (clear) {
+        const int rc = launch_fill_u32(ranges, size_t(tiles_total) * 2, 0u, s);
+        if (rc != VRS_OK) return rc;
+    }
     if (capacity == 0) return VRS_OK;
     const size_t blocks = (capacity + 255) / 256;
     hipLaunchKernelGGL(k_tile_ranges, dim3(blocks < 8192 ? blocks : 8192), dim3(256), 0, s, keys, n_dev, capacity,
