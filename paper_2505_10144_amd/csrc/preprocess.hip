@@ -243,6 +243,7 @@ __global__ void __launch_bounds__(64) k_duplicate(GaussPtrs g, GeoViews views, K
     __shared__ uint32_t pre[65];
     __shared__ GeoView vw[kViews];  // the views the block's slots fall in, from v_lo
     __shared__ TileGeo tgl[64];
+    __shared__ int mark[64];
     // No candidates, or more than the 32-bit offsets can address (the scan
     // then reports the overflow and leaves a total of 0): nothing to write.
     if (n_inst[0] == 0u) return;
@@ -254,6 +255,10 @@ __global__ void __launch_bounds__(64) k_duplicate(GaussPtrs g, GeoViews views, K
         if (lane == 0) vw[v - v_lo] = views.v[v];
     const size_t s = s0 + lane;
     const uint32_t c = s < nslots ? counts[s] : 0u;
+    // This slot's tile rectangle, as four words that the candidates' lanes
+    // fetch from the owner's lane.
+    uint4 myrc = make_uint4(0u, 0u, 0u, 0u);
+    if (c > 0) myrc = reinterpret_cast<const uint4*>(rects)[s];
     uint32_t incl = c;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -279,25 +284,37 @@ __global__ void __launch_bounds__(64) k_duplicate(GaussPtrs g, GeoViews views, K
     }
     __syncthreads();
     const uint32_t total = pre[64];
+    const uint32_t my0 = incl - c;  // this slot's first candidate in the block
     const size_t base = offsets[s0];
     for (uint32_t j0 = 0; j0 < total; j0 += 64) {
+        // Owner of candidate j0 + lane: every slot with candidates in this
+        // window marks where its run enters it; the owner is the last mark at
+        // or before the lane (a running maximum, the slots being in order).
+        mark[lane] = -1;
+        __syncthreads();
+        if (c > 0 && my0 < j0 + 64u && my0 + c > j0) mark[(my0 > j0 ? my0 : j0) - j0] = lane;
+        __syncthreads();
+        int ow = mark[lane];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(ow, d);
+            if (lane >= d) ow = max(ow, y);
+        }
+        __syncthreads();  // (the marks are read before the next window's reset)
+        TileRect rc;
+        {
+            const uint4 r4 = make_uint4(__shfl(myrc.x, ow), __shfl(myrc.y, ow), __shfl(myrc.z, ow), __shfl(myrc.w, ow));
+            memcpy(&rc, &r4, sizeof(rc));
+        }
         const uint32_t j = j0 + lane;
         bool kept;
         const size_t cg = base + j;
         if (j < total && cg < capacity) {
-            int lo = 0, hi = 64;  // last owner l with pre[l] <= j
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (pre[mid] <= j) lo = mid + 1;
-                else hi = mid;
-            }
-            const int ow = lo - 1;
             const size_t o = s0 + ow;
             const int v = int(o / size_t(n));
             const int i = int(o - size_t(v) * size_t(n));
             const GeoView& V = vw[v - v_lo];
             const TileGeo& tg = tgl[ow];
-            const TileRect rc = rects[o];
             const int k = int(j - pre[ow]);
             int tx, ty;
             kth_tile(V, rc, k, tx, ty);
