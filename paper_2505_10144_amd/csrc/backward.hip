@@ -750,8 +750,10 @@ __global__ void __launch_bounds__(256) k_color_bwd(GaussPtrs g, GeoViews views, 
 }
 
 // K8b, geometry part: means (added to the colour part), log-scales,
-// quaternions and opacity logits.
-__global__ void __launch_bounds__(128) k_geom_bwd(GaussPtrs g, GeoViews views, Knobs kn,
+// quaternions and opacity logits.  The FP64 dual numbers take every register
+// a wave can have; held to two waves per SIMD, the kernel spills a few
+// values and runs faster than at one.
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) k_geom_bwd(GaussPtrs g, GeoViews views, Knobs kn,
                                                   const float* __restrict__ grad2d, GradPtrs out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
