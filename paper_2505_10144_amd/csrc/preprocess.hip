@@ -398,11 +398,18 @@ int launch_duplicate(const GaussPtrs& g, const GeoViews& views, const Knobs& kn,
     const size_t nslots = size_t(g.n) * size_t(views.n);
     uint32_t* offsets = static_cast<uint32_t*>(ws);
     uint32_t* tmp = offsets + nslots;
-    int rc = launch_exclusive_scan(counts, offsets, nslots, n_inst, tmp, status, s);
-    if (rc != VRS_OK) return rc;
-    const size_t clear_blocks = (n_clear + 255) / 256;
-    hipLaunchKernelGGL(k_dup_init, dim3(clear_blocks == 0 ? 1 : (clear_blocks < 1024 ? clear_blocks : 1024)),
-                       dim3(256), 0, s, n_inst, capacity, status, clear, n_clear);
+    // Candidate offsets, the candidate total in n_inst[0], and the set-up
+    // below, in two launches where the scan is small enough.
+    int rc = launch_scan_with_setup(counts, offsets, nslots, n_inst, tmp, capacity, status, clear, n_clear, s);
+    if (rc == VRS_ERR_UNSUPPORTED) {
+        rc = launch_exclusive_scan(counts, offsets, nslots, n_inst, tmp, status, s);
+        if (rc != VRS_OK) return rc;
+        const size_t clear_blocks = (n_clear + 255) / 256;
+        hipLaunchKernelGGL(k_dup_init, dim3(clear_blocks == 0 ? 1 : (clear_blocks < 1024 ? clear_blocks : 1024)),
+                           dim3(256), 0, s, n_inst, capacity, status, clear, n_clear);
+    } else if (rc != VRS_OK) {
+        return rc;
+    }
     if (nslots == 0 || capacity == 0) return launch_status(hipGetLastError());
     const TileRect* rects =
         reinterpret_cast<const TileRect*>(reinterpret_cast<const char*>(proj) + rect_offset_bytes(nslots));

@@ -635,10 +635,14 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
 // that length on a log scale with 16 steps per octave.  One block does a
 // counting sort by that key, longest first: an LDS histogram, its scan,
 // then every item takes the next slot of its key's run with an LDS atomic.
-// The order within a run depends on timing, which does not matter: every
-// item writes only its own pixels.
+// Each key's run is split into kOrderSub parts by thread (thread mod
+// kOrderSub), with a counter each, so that the many items of a popular key
+// do not all update one LDS word.  The order within a run depends on
+// timing, which does not matter: every item writes only its own pixels.
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderPer = 16;  // items a thread has in flight
+constexpr int kOrderSub = 4;
+static_assert(256 * kOrderSub == kOrderThreads, "one (key, part) counter per thread in the scan");
 
 __device__ inline uint32_t cost_key(uint2 rg) {
     const uint32_t c = rg.y - rg.x;
@@ -655,13 +659,14 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
                                                                const uint32_t* __restrict__ count_dev,
                                                                uint32_t n_max, const uint32_t* __restrict__ ranges,
                                                                RenderViews views, uint32_t* __restrict__ out) {
-    __shared__ uint32_t cnt[256];
-    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t cnt[256 * kOrderSub];  // (key, part), key-major
+    __shared__ uint32_t wsum[kOrderThreads / 64];
     __shared__ uint32_t toff[VRS_MAX_VIEWS];  // each view's first global tile
     const int t = threadIdx.x;
+    const uint32_t part = uint32_t(t % kOrderSub);
     const uint32_t n = min(*count_dev, n_max);
     constexpr uint32_t kChunk = uint32_t(kOrderThreads * kOrderPer);
-    if (t < 256) cnt[t] = 0;
+    cnt[t] = 0;
     if (t < views.n) toff[t] = views.v[t].tile_off;
     __syncthreads();
     const uint2* rgs = reinterpret_cast<const uint2*>(ranges);
@@ -689,7 +694,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
     keys_of(0u, it0, key0);
 #pragma unroll
     for (int j = 0; j < kOrderPer; ++j)
-        if (uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[key0[j]], 1u);
+        if (uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[key0[j] * kOrderSub + part], 1u);
     for (uint32_t c0 = kChunk; c0 < n; c0 += kChunk) {
         uint32_t it[kOrderPer], key[kOrderPer];
 #pragma unroll
@@ -700,14 +705,13 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
         keys_of(c0, it, key);
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j)
-            if (c0 + uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[key[j]], 1u);
+            if (c0 + uint32_t(j * kOrderThreads + t) < n) atomicAdd(&cnt[key[j] * kOrderSub + part], 1u);
     }
     __syncthreads();
-    // Exclusive scan of the 256 counts by the first four waves.
-    uint32_t x = 0, v = 0;
-    if (t < 256) {
-        x = cnt[t];
-        v = x;
+    // Exclusive scan of the (key, part) counts, one per thread.
+    const uint32_t x = cnt[t];
+    uint32_t v = x;
+    {
         const int lane = t & 63;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -717,7 +721,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
         if (lane == 63) wsum[t >> 6] = v;
     }
     __syncthreads();
-    if (t < 256) {
+    {
         uint32_t pre = 0;
         for (int k = 0; k < (t >> 6); ++k) pre += wsum[k];
         cnt[t] = pre + v - x;
@@ -725,7 +729,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kOrderPer; ++j)
-        if (uint32_t(j * kOrderThreads + t) < n) out[atomicAdd(&cnt[key0[j]], 1u)] = it0[j];
+        if (uint32_t(j * kOrderThreads + t) < n) out[atomicAdd(&cnt[key0[j] * kOrderSub + part], 1u)] = it0[j];
     for (uint32_t c0 = kChunk; c0 < n; c0 += kChunk) {
         uint32_t it[kOrderPer], key[kOrderPer];
 #pragma unroll
@@ -736,7 +740,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
         keys_of(c0, it, key);
 #pragma unroll
         for (int j = 0; j < kOrderPer; ++j)
-            if (c0 + uint32_t(j * kOrderThreads + t) < n) out[atomicAdd(&cnt[key[j]], 1u)] = it[j];
+            if (c0 + uint32_t(j * kOrderThreads + t) < n) out[atomicAdd(&cnt[key[j] * kOrderSub + part], 1u)] = it[j];
     }
 }
 

@@ -145,6 +145,56 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(uint32_t* __restrict_
         if (base + k < n) out[base + k] += add;
 }
 
+// The second half of a scan of at most kScanFusedTiles tiles in one launch,
+// fused with instantiation's set-up: every block sums the tile sums before
+// its own (in 64 bits, from L2) and adds that to its tile; block 0 stores the
+// grand total in n_inst[0] -- 0, with the overflow reported, when it reaches
+// 2^32 - 1 (a saturated tile sum does) -- zeroes n_inst[1] and reports a
+// total above `capacity`; every block clears a share of `clear`.
+constexpr size_t kScanFusedTiles = 4096;
+__global__ void __launch_bounds__(kScanThreads) k_scan_add_setup(uint32_t* __restrict__ out,
+                                                                 const uint32_t* __restrict__ sums, size_t n,
+                                                                 size_t nb, uint32_t* __restrict__ n_inst,
+                                                                 size_t capacity, int* status,
+                                                                 uint32_t* __restrict__ clear, size_t n_clear) {
+    __shared__ uint64_t sh64[kScanThreads / 64];
+    uint64_t before = 0, all = 0;
+    for (size_t k = threadIdx.x; k < nb; k += kScanThreads) {
+        const uint32_t v = sums[k];
+        all += v;
+        before += k < size_t(blockIdx.x) ? v : 0u;
+    }
+    before = block_sum_u64(before, sh64);
+    all = block_sum_u64(all, sh64);
+    const uint32_t add = uint32_t(before);
+    const size_t base = size_t(blockIdx.x) * kScanTile;
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+        if (base + k < n) out[base + k] += add;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const bool over = all >= 0xFFFFFFFFull;
+        if (over) set_status(status, VRS_ERR_UNSUPPORTED);
+        const uint32_t tot = over ? 0u : uint32_t(all);
+        n_inst[0] = tot;
+        n_inst[1] = 0;
+        if (size_t(tot) > capacity) set_status(status, VRS_ERR_CAPACITY);
+    }
+    for (size_t i = size_t(blockIdx.x) * kScanThreads + threadIdx.x; i < n_clear; i += size_t(gridDim.x) * kScanThreads)
+        clear[i] = 0u;
+}
+
+// Exclusive scan of n > 0 words in two launches when it spans at most
+// kScanFusedTiles tiles, with instantiation's set-up (see k_scan_add_setup);
+// returns VRS_ERR_UNSUPPORTED without launching anything otherwise.
+int launch_scan_with_setup(const uint32_t* in, uint32_t* out, size_t n, uint32_t* n_inst, uint32_t* tmp,
+                           size_t capacity, int* status, uint32_t* clear, size_t n_clear, hipStream_t s) {
+    const size_t nb = (n + kScanTile - 1) / kScanTile;
+    if (n == 0 || nb > kScanFusedTiles) return VRS_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanThreads), 0, s, in, out, tmp, n);
+    hipLaunchKernelGGL(k_scan_add_setup, dim3(nb), dim3(kScanThreads), 0, s, out, tmp, n, nb, n_inst, capacity, status,
+                       clear, n_clear);
+    return launch_status(hipGetLastError());
+}
+
 __global__ void k_store_zero(uint32_t* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -172,13 +222,21 @@ __device__ inline size_t n_eff(const uint32_t* n_dev, size_t capacity) {
     return n < capacity ? n : capacity;
 }
 
+// Digit counts go to kSubHist copies of the histogram by lane (lane mod
+// kSubHist), summed at the end: a byte that takes few values (the top byte of
+// the depths, the high byte of the tiles) would otherwise put many lanes of
+// one atomic instruction on the same LDS word, which serializes them.
+constexpr int kSubHist = 4;
+
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __restrict__ keys,
                                                              const uint32_t* __restrict__ n_dev,
                                                              size_t capacity, int shift, int drop,
                                                              uint32_t* __restrict__ hist, int nblocks) {
-    __shared__ uint32_t cnt[kRadix];
-    cnt[threadIdx.x] = 0;
+    __shared__ uint32_t cnt[kSubHist][kRadix];
+#pragma unroll
+    for (int c = 0; c < kSubHist; ++c) cnt[c][threadIdx.x] = 0;
     __syncthreads();
+    const int sub = threadIdx.x % kSubHist;
     const size_t n = n_eff(n_dev, capacity);
     const size_t base = size_t(blockIdx.x) * kSortTile;
     // Every load is issued before the first count, so the wave waits for
@@ -192,10 +250,13 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __r
 #pragma unroll
     for (int k = 0; k < kSortItemsPerLane; ++k) {
         const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
-        if (idx < n && !(drop && key[k] == kDeadKey)) atomicAdd(&cnt[uint32_t(key[k] >> shift) & 0xFFu], 1u);
+        if (idx < n && !(drop && key[k] == kDeadKey)) atomicAdd(&cnt[sub][uint32_t(key[k] >> shift) & 0xFFu], 1u);
     }
     __syncthreads();
-    hist[size_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    uint32_t c = 0;
+#pragma unroll
+    for (int s = 0; s < kSubHist; ++s) c += cnt[s][threadIdx.x];
+    hist[size_t(threadIdx.x) * nblocks + blockIdx.x] = c;
 }
 
 __device__ inline uint64_t lanemask_lt() {
@@ -304,9 +365,11 @@ __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* _
                                                                uint32_t* __restrict__ live_out,
                                                                uint32_t* __restrict__ totals,
                                                                uint32_t* __restrict__ hist0) {
-    __shared__ uint32_t cnt[kMaxPasses][kRadix];
+    __shared__ uint32_t cnt[kMaxPasses][kSubHist][kRadix];
     __shared__ uint32_t wlive[kSortWaves];
-    for (int p = 0; p < kMaxPasses; ++p) cnt[p][threadIdx.x] = 0;
+    const int sub = threadIdx.x % kSubHist;
+    for (int p = 0; p < passes; ++p)
+        for (int s = 0; s < kSubHist; ++s) cnt[p][s][threadIdx.x] = 0;
     // The digit totals that k_digit_totals adds up next start at zero.
     if (blockIdx.x == 0)
         for (int p = 0; p < passes; ++p) totals[p * kRadix + threadIdx.x] = 0;
@@ -325,7 +388,7 @@ __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* _
         const size_t idx = base + size_t(k) * kSortThreads + threadIdx.x;
         if (idx < n && !(drop && key[k] == kDeadKey)) {
             ++live;
-            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][uint32_t(key[k] >> (8 * p)) & 0xFFu], 1u);
+            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][sub][uint32_t(key[k] >> (8 * p)) & 0xFFu], 1u);
         }
     }
     if (live_out) {  // uniform
@@ -338,11 +401,17 @@ __global__ void __launch_bounds__(kSortThreads) k_digit_counts(const uint64_t* _
         for (int w = 0; w < kSortWaves; ++w) b += wlive[w];
         if (b) atomicAdd(live_out, b);
     }
-    for (int p = 0; p < passes; ++p)
-        counts[(size_t(p) * nblocks + blockIdx.x) * kRadix + threadIdx.x] = cnt[p][threadIdx.x];
+    uint32_t c0 = 0;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int s = 0; s < kSubHist; ++s) c += cnt[p][s][threadIdx.x];
+        counts[(size_t(p) * nblocks + blockIdx.x) * kRadix + threadIdx.x] = c;
+        if (p == 0) c0 = c;
+    }
     // The first pass's counts once more, digit-major as the later passes'
     // histograms are, so that its row scan reads whole rows.
-    hist0[size_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[0][threadIdx.x];
+    hist0[size_t(threadIdx.x) * nblocks + blockIdx.x] = c0;
 }
 
 // Digit totals of every pass: block (r, p) adds rows [32r, 32r + 32) of

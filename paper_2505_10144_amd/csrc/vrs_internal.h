@@ -322,5 +322,12 @@ size_t scan_tmp_words(size_t n);
 // sets *total to 0 and writes VRS_ERR_UNSUPPORTED to *status (if non-null).
 int launch_exclusive_scan(const uint32_t* in, uint32_t* out, size_t n, uint32_t* total, uint32_t* tmp,
                           int* status, hipStream_t s);
+// The same scan in two launches for 0 < n <= 4096 tiles of 2048 words (else
+// VRS_ERR_UNSUPPORTED and nothing launched), fused with instantiation's
+// set-up: the total goes to n_inst[0] (0 on overflow, as above), n_inst[1]
+// is zeroed, a total above `capacity` writes VRS_ERR_CAPACITY to *status,
+// and clear[0, n_clear) is zeroed.
+int launch_scan_with_setup(const uint32_t* in, uint32_t* out, size_t n, uint32_t* n_inst, uint32_t* tmp,
+                           size_t capacity, int* status, uint32_t* clear, size_t n_clear, hipStream_t s);
 
 }  // namespace vrs
