@@ -132,8 +132,9 @@ typedef struct {
  * window: per-sample resort window length W, 0..32 (Sec. 4.1; 0 blends in
  * key order without resorting, like the global-sort comparison renderers of
  * Sec. 5); depth_mode: one of VRS_DEPTH_* (the key depth); blend_batch:
- * list entries staged per wave and batch, 16, 32 or 64, and schedule, one
- * of VRS_SCHEDULE_* (both performance only, never changing the output).
+ * list entries staged per wave and batch, 16, 32 or 64 (the forward blend
+ * stages at most 56 at a time), and schedule, one of VRS_SCHEDULE_* (both
+ * performance only, never changing the output).
  * z_near: near cull on camera z; alpha_min: culling and skip threshold
  * (1/255, Sec. 4.2); alpha_max: alpha clamp (0.99); t_min: transmittance at
  * which a sample stops (1e-4); dilation: px^2 added to the 2D covariance
