@@ -468,8 +468,8 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU rendering is a design "
-                                   "(views or screen tiles per GPU) and is not measured",
+        print(json.dumps({"error": "the renderer runs on one GPU only; multi-GPU rendering (views or screen "
+                                   "tiles per GPU) is a design that is not implemented or measured",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
