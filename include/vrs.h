@@ -346,9 +346,10 @@ typedef struct {
 } vrs_gaussian_grads;
 
 /* Workspace bytes of vrs_render_backward: per view and Gaussian, 12 FP32
- * gradients of the render record, and per foveated view three [4][H][W]
- * FP32 planes (its samples' forward values, dL/d(pre-compose image),
- * dL/d(sample)).  0 for invalid arguments. */
+ * gradients of the render record, per foveated view three [4][H][W] FP32
+ * planes (its samples' forward values, dL/d(pre-compose image),
+ * dL/d(sample)), and the work items in longest-first order.  0 for invalid
+ * arguments. */
 size_t vrs_backward_workspace_size(int32_t n, const vrs_camera* cams, const vrs_fovea* foveas,
                                    int32_t n_views, const vrs_params* p);
 

@@ -538,11 +538,16 @@ namespace {
 // (HYBRID unmixed), dL/d(pre-compose image) and dL/d(sample).
 size_t bwd_fov_off(size_t n, int n_views) { return (backward_ws_bytes(n, n_views) + 255) & ~size_t(255); }
 
-size_t bwd_ws_total(size_t n, const vrs_camera* cams, const vrs_fovea* foveas, int n_views) {
+// Then the work items in longest-first order (the ordering area of the blend).
+size_t bwd_order_off(size_t n, const vrs_camera* cams, const vrs_fovea* foveas, int n_views) {
     size_t b = bwd_fov_off(n, n_views);
     for (int v = 0; v < n_views; ++v)
         if (foveas[v].enabled) b += 3 * 4 * size_t(cams[v].width) * size_t(cams[v].height) * sizeof(float);
-    return b;
+    return (b + 255) & ~size_t(255);
+}
+
+size_t bwd_ws_total(size_t n, const vrs_camera* cams, const vrs_fovea* foveas, int n_views, size_t items_max) {
+    return bwd_order_off(n, cams, foveas, n_views) + order_ws_bytes(items_max);
 }
 
 }  // namespace
@@ -553,7 +558,7 @@ size_t vrs_backward_workspace_size(int32_t n, const vrs_camera* cams, const vrs_
                                    const vrs_params* p) {
     Layout L;
     if (n < 0 || make_layout(cams, foveas, n_views, p, L) != VRS_OK) return 0;
-    return bwd_ws_total(size_t(n), cams, foveas, n_views);
+    return bwd_ws_total(size_t(n), cams, foveas, n_views, size_t(L.items_max));
 }
 
 int vrs_render_backward(const vrs_gaussians* g, const void* proj, const uint32_t* gids, const uint32_t* ranges,
@@ -575,11 +580,11 @@ int vrs_render_backward(const vrs_gaussians* g, const void* proj, const uint32_t
         if (!proj || !gids || !ranges || !aligned(proj, 16)) return VRS_ERR_INVALID_ARG;
         if (!out->means || !out->log_scales || !out->quats || !out->opacity_logits || !out->sh)
             return VRS_ERR_INVALID_ARG;
-        if (!ws || !aligned(ws, 256) || ws_bytes < bwd_ws_total(size_t(g->n), cams, foveas, n_views))
+        if (!ws || !aligned(ws, 256) || ws_bytes < bwd_ws_total(size_t(g->n), cams, foveas, n_views, L.items_max))
             return VRS_ERR_INVALID_ARG;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const uint32_t* items = plan_items(plan);
+    const uint32_t* items = plan_items(plan);  // longest first once ordered below
     BwdViews B;
     memset(&B, 0, sizeof(B));
     B.n = n_views;
@@ -625,6 +630,14 @@ int vrs_render_backward(const vrs_gaussians* g, const void* proj, const uint32_t
         F.mask = make_fov_mask(cams[v], foveas[v]);
         rc = launch_fov_grads(F, s);
         if (rc != VRS_OK) return rc;
+    }
+    if (g->n > 0 && n_items > 0) {
+        // The same longest-first order as the forward's: the replay blocks
+        // are long, and the longest last would extend the launch.
+        items = launch_order_items(plan_items(plan), n_items, static_cast<const uint32_t*>(plan), L.items_max, ranges,
+                                   R, static_cast<char*>(ws) + bwd_order_off(size_t(g->n), cams, foveas, n_views),
+                                   nullptr, s);
+        if (!items) return VRS_ERR_HIP;
     }
     if (any_fov && g->n > 0 && n_items > 0) {
         // The foveated views' samples as the forward blended them (HYBRID
