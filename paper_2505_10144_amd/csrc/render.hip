@@ -634,8 +634,9 @@ int launch_blend(const float* proj, uint32_t n_gauss, const uint32_t* gids, cons
 
 // Longest-first order of the work items (list scheduling: the blocks that
 // take longest start first, so they do not extend the end of the launch).
-// The cost of an item is the length of its sort tile's list; the key is
-// that length on a log scale with 16 steps per octave.  One block does a
+// The cost of an item is the length of its sort tile's list (halved for a
+// subtile, see cost_key); the key is that cost on a log scale with 16 steps
+// per octave.  One block does a
 // counting sort by that key, longest first: an LDS histogram, its scan,
 // then every item takes the next slot of its key's run with an LDS atomic.
 // Each key's run is split into kOrderSub parts by thread (thread mod
@@ -647,8 +648,11 @@ constexpr int kOrderPer = 16;  // items a thread has in flight
 constexpr int kOrderSub = 4;
 static_assert(256 * kOrderSub == kOrderThreads, "one (key, part) counter per thread in the scan");
 
-__device__ inline uint32_t cost_key(uint2 rg) {
-    const uint32_t c = rg.y - rg.x;
+// `sub`: a 16x16 subtile of a 32x32 sort tile, whose waves cull its list to
+// 8x8-pixel rectangles and so evaluate about half the entries a LOW item of
+// the same list does; its cost is taken as half its list length.
+__device__ inline uint32_t cost_key(uint2 rg, bool sub) {
+    const uint32_t c = sub ? (rg.y - rg.x) >> 1 : rg.y - rg.x;
     uint32_t b = 0;
     if (c != 0) {
         const int e = 31 - __clz(int(c));
@@ -682,7 +686,10 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint32_t* _
             if (c0 + uint32_t(j * kOrderThreads + t) < n) rg[j] = rgs[toff[item_view(it[j])] + item_tile(it[j])];
         }
 #pragma unroll
-        for (int j = 0; j < kOrderPer; ++j) key[j] = cost_key(rg[j]);
+        for (int j = 0; j < kOrderPer; ++j) {
+            const RenderView& V = views.v[item_view(it[j])];
+            key[j] = cost_key(rg[j], item_class(it[j]) != VRS_CLASS_LOW && (V.foveated || V.T == 32));
+        }
     };
     // Each thread keeps kOrderPer items (and their list-range loads) in
     // flight at a time.  The first chunk's items and keys stay in registers
